@@ -1,0 +1,224 @@
+/*
+ * twolink.h -- C ABI of libtwolink.so: two-link staggered Gaussian smearing
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Gottlieb, Jeong, Strelchenko, arXiv:2301.05518, Sec. 2 and 3):
+ *   two-link product    W_mu(x) = U_mu(x) U_mu(x+mu^),  mu = x, y, z
+ *   two-link Laplacian  4 Lap psi(x) = sum_mu [W_mu(x) psi(x+2mu^)
+ *                                       + W_mu^dag(x-2mu^) psi(x-2mu^)] - 6 psi(x)   (eq. tlLapl1)
+ *   smearing            psi <- (1 + (sigma/n) Lap)^n psi                            (eq. tlSmear)
+ * The Laplacian is three-dimensional: it acts on one time slice and never
+ * hops in t.  Boundaries are periodic in x, y and z.  W is built once per
+ * gauge field and reused for every source and sink (Sec. 3).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Return value: TL_OK (0) or a negative TL_ERR_* code.  tl_last_error()
+ *   gives a message.  Argument errors are detected before any device work
+ *   is queued, and nothing is written in that case.  No C++ exception
+ *   crosses this interface.
+ * - Asynchrony: device work is queued on the context's stream and the call
+ *   returns without waiting, unless stated otherwise.  Errors raised by the
+ *   device afterwards surface at tl_sync() or at a later call.
+ * - Ownership: the caller owns every buffer passed in (gauge field, two-link
+ *   field, colour-vector fields, outputs).  The library never frees them and
+ *   keeps no pointer to them after the call returns, except that a plan
+ *   (tl_plan_*) keeps the job pointers given to tl_plan_create until
+ *   tl_plan_destroy.  Library-internal memory (resident packed fields,
+ *   work lists, reduction partials, scratch) belongs to the context or plan.
+ * - "device" pointers are HIP device memory of the context's device;
+ *   "host" pointers are ordinary host memory read during the call.
+ * - Geometry: tl_geom.L = {Lx, Ly, Lz, Lt}, every extent in [1, 4096] and
+ *   Lx*Ly*Lz <= 2^27.
+ * - Natural layouts (complex128 = two doubles, real part first):
+ *     gauge field U       [Lt][Lz][Ly][Lx][mu=0..3][a][b]   mu = x, y, z, t
+ *                         U_mu(x) transports a vector from x+mu^ to x.
+ *     colour vectors psi  [n_rhs][Lz][Ly][Lx][c]            one slice per RHS
+ *   The two-link field W is an opaque packed buffer in the storage
+ *   precision it was built in; size it with tl_twolinks_bytes().
+ * - Storage precisions: TL_F64 (FP64 storage and arithmetic), TL_F32,
+ *   TL_F16S (IEEE half times one FP32 scale per site), TL_BF16; the last
+ *   three use FP32 arithmetic.  The two-link product is always formed in
+ *   FP64 and rounded to the storage precision when stored.  Reductions
+ *   accumulate in FP64.
+ */
+#ifndef TWOLINK_H
+#define TWOLINK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+enum {
+    TL_OK = 0,
+    TL_ERR_ARG = -1,         /* null pointer, bad count, bad flag or kind, aliasing */
+    TL_ERR_SHAPE = -2,       /* geometry out of range, slice not present in W */
+    TL_ERR_PRECISION = -3,   /* unknown storage precision */
+    TL_ERR_DEVICE = -4,      /* no such device, or device work on a host-only context */
+    TL_ERR_HIP = -5,         /* a HIP runtime call failed (message from the runtime) */
+    TL_ERR_NOMEM = -6,       /* a library-internal device allocation failed */
+    TL_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+};
+
+enum { TL_F64 = 0, TL_F32 = 1, TL_F16S = 2, TL_BF16 = 3 };
+
+/* tl_smear / tl_plan_create flags */
+enum {
+    TL_PLAIN = 1u,      /* one right-hand side per launch, RHS in succession, eager launches */
+    TL_GRAPH = 2u,      /* capture the n step launches in one HIP graph, replayed per run */
+    TL_AUTOTUNE = 4u    /* time the candidate tilings once and keep the fastest (cached per context) */
+};
+
+/* reduction kinds */
+enum {
+    TL_NORM2 = 0,       /* per RHS: sum_x |psi(x)|^2                -> out[n_rhs] */
+    TL_DOT = 1,         /* per RHS: sum_x phi(x)^dag psi(x)         -> out[2*n_rhs] (re, im) */
+    TL_SITE_NORM = 2    /* per RHS and site: |psi(x)| (Fig. 1 quantity) -> out[n_rhs*V3] */
+};
+
+typedef struct { int32_t L[4]; } tl_geom;   /* Lx, Ly, Lz, Lt */
+
+typedef struct tl_ctx tl_ctx;
+typedef struct tl_plan tl_plan;
+
+/* One lattice's share of a smearing batch. */
+typedef struct {
+    tl_geom g;
+    const void *W;             /* device: two-link field built in the batch's precision */
+    const int32_t *w_slices;   /* host: slice list W was built for; NULL = all Lt slices in order */
+    int32_t n_w_slices;        /* entries in w_slices (ignored when w_slices is NULL) */
+    int32_t n_rhs;             /* right-hand sides of this lattice, >= 1 */
+    const int32_t *t_of_rhs;   /* host: time slice of each RHS, n_rhs entries, each in W */
+    void *psi;                 /* device: complex128 [n_rhs][Lz][Ly][Lx][3], smeared in place */
+} tl_job;
+
+/* What a plan resolved to (filled by tl_plan_get_info). */
+typedef struct {
+    int32_t n_groups;          /* RHS groups: RHS of one slice that share each W load */
+    int32_t group_width;       /* largest group */
+    int32_t n_tiles;           /* work-list entries per step */
+    int32_t variant;           /* step kernel variant (0 direct, 1 z-marching) */
+    int32_t block;             /* threads per workgroup */
+    int32_t tz;                /* z planes per tile */
+    int32_t grid;              /* workgroups per step launch */
+    int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN */
+    int64_t rhs_sites;         /* sum over RHS of Lx*Ly*Lz */
+    double bytes_per_step;     /* algorithmic bytes of one step: W once per group + psi in and out */
+    double flops_per_step;     /* 444 per RHS-site-update */
+    int64_t resident_bytes;    /* device memory the plan holds */
+} tl_plan_info;
+
+/* ---------------------------------------------------------------- context */
+
+/* Library version, major*10000 + minor*100 + patch. */
+int tl_version(void);
+
+/*
+ * Create a context on HIP device `device`, queueing on `stream` (a
+ * hipStream_t; NULL = the null stream).  device = -1 creates a host-only
+ * context that validates arguments and answers size queries but returns
+ * TL_ERR_DEVICE for any device work.  *out receives the context.
+ */
+int tl_create(tl_ctx **out, int device, void *stream);
+int tl_destroy(tl_ctx *ctx);
+int tl_set_stream(tl_ctx *ctx, void *stream);
+/* Block until the context's stream is idle; reports asynchronous device errors. */
+int tl_sync(tl_ctx *ctx);
+/* Message of the last failing call on ctx (ctx = NULL: last failure of tl_create on this thread). */
+const char *tl_last_error(const tl_ctx *ctx);
+
+/* ------------------------------------------------------------------ sizes */
+
+/* TL_OK if g is a supported geometry, TL_ERR_SHAPE (or TL_ERR_ARG for NULL) otherwise. */
+int tl_check_geom(const tl_geom *g);
+/* Bytes of a two-link field for n_slices slices in precision prec (0 on bad arguments). */
+size_t tl_twolinks_bytes(const tl_geom *g, int prec, int n_slices);
+
+/* ---------------------------------------------------------------- the path */
+
+/*
+ * Two-link product (Sec. 2; precomputed once per gauge field, Sec. 3):
+ * W_mu(x) = U_mu(x) U_mu(x+mu^) for mu = x, y, z at every site of the listed
+ * slices, formed in FP64 and stored in precision `prec`.
+ *   U        device, complex128 natural gauge field of geometry g (only the
+ *            spatial links of the listed slices are read)
+ *   slices   host, n_slices slice indices, each in [0, Lt), no repeats;
+ *            NULL = all Lt slices in order (n_slices must then be Lt or 0)
+ *   W        device, tl_twolinks_bytes(g, prec, n_slices) bytes, written;
+ *            slot j holds slice slices[j]
+ */
+int tl_build_twolinks(tl_ctx *ctx, const tl_geom *g, const void *U,
+                      const int32_t *slices, int n_slices, int prec, void *W);
+
+/*
+ * One application of the two-link Laplacian of eq. tlLapl1 (including the
+ * factor 1/4 and the -6 term) on time slice t:  out = Lap in.
+ *   W, w_slices, n_w_slices  as in tl_job; t must be one of W's slices
+ *   in, out  device complex128 [Lz][Ly][Lx][3]; out must not overlap in
+ * `in` is rounded to the storage precision first; the arithmetic is FP64 for
+ * TL_F64 and FP32 otherwise; the result is rounded to the storage precision
+ * and then widened to complex128.  Uses context scratch memory.
+ */
+int tl_laplacian(tl_ctx *ctx, const tl_geom *g, const void *W, const int32_t *w_slices,
+                 int n_w_slices, int prec, int t, const void *in, void *out);
+
+/*
+ * Smearing of eq. tlSmear, psi <- (1 + (sigma/n) Lap)^n psi with n = n_steps,
+ * applied in place to every right-hand side of every job on its own slice.
+ * Jobs may have different geometries (uneven batch).  Equivalent to
+ * tl_plan_create + load + run + store + destroy.  Requires n_steps >= 0,
+ * finite sigma with 0 <= sigma/n_steps <= 2/3 (the step is then a contraction).
+ */
+int tl_smear(tl_ctx *ctx, const tl_job *jobs, int n_jobs, int n_steps, double sigma,
+             int prec, unsigned flags);
+
+/* ------------------------------------------------------- resident plans */
+
+/*
+ * A plan holds the batch's colour vectors resident on the device in packed
+ * storage precision, the step work list, the tuned tiling and (TL_GRAPH) the
+ * captured step graph, so that repeated runs pay none of that again.
+ * The jobs array (and the host arrays it points to) is copied; the device
+ * pointers in it (W, psi) must stay valid until tl_plan_destroy.
+ */
+int tl_plan_create(tl_ctx *ctx, const tl_job *jobs, int n_jobs, int n_steps, double sigma,
+                   int prec, unsigned flags, tl_plan **out);
+/* Pack every job's psi (complex128) into the resident buffer (rounds to the storage precision). */
+int tl_plan_load(tl_plan *plan);
+/* n_steps smearing steps on the resident buffer. */
+int tl_plan_run(tl_plan *plan);
+/* Unpack the resident buffer into every job's psi (complex128). */
+int tl_plan_store(tl_plan *plan);
+/*
+ * FP64 reduction of the resident fields (decoded from storage precision),
+ * deterministic summation order.  kind: TL_NORM2, TL_DOT (needs `other`, a
+ * plan with the same jobs' shapes; <other, this> per RHS), TL_SITE_NORM.
+ * out: device doubles, sized as for the kind (RHS in the order of the jobs).
+ */
+int tl_plan_reduce(tl_plan *plan, int kind, const tl_plan *other, double *out);
+/* Average device time of one step kernel launch over `reps` back-to-back
+ * runs of n_steps steps each, measured with HIP events on the context's
+ * stream (blocks the host).  The resident fields are smeared further. */
+int tl_plan_time(tl_plan *plan, int reps, double *ms_per_step);
+int tl_plan_get_info(const tl_plan *plan, tl_plan_info *info);
+int tl_plan_destroy(tl_plan *plan);
+
+/* -------------------------------------------------------- reductions */
+
+/*
+ * FP64 reductions of natural complex128 fields psi, phi [n_rhs][n_sites][3]
+ * (device).  kind as above; phi only for TL_DOT (<phi, psi> per RHS).
+ * out: device doubles (n_rhs, 2*n_rhs or n_rhs*n_sites entries).
+ */
+int tl_reduce(tl_ctx *ctx, int kind, int64_t n_sites, int n_rhs, const void *psi,
+              const void *phi, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TWOLINK_H */

@@ -1,0 +1,222 @@
+// Packed storage formats of the two-link field and of colour vectors.
+//
+// Every field is a set of planes; a plane holds one fixed-width word per site
+// (sites in [z][y][x] order, plane length Vp), so a wavefront reading 64
+// consecutive sites of a plane issues one fully coalesced vector load.
+// Reals are kept in the order (re0, im0, re1, im1, ...): for a 3x3 matrix
+// element k = 3a + b, for a colour vector component c.
+//
+//   precision  two-link field per site and direction        colour vector per site
+//   FP64       9 planes double2 (one complex each)   144 B   3 planes double2      48 B
+//   FP32       4 planes float4 + 1 plane float2        72 B   float4 + float2       24 B
+//   F16S       2 planes 8 x half + 1 plane            40 B   1 plane: 6 x half     16 B
+//              (2 x half, FP32 scale)                        + FP32 scale
+//   BF16       2 planes 8 x bf16 + 1 plane 2 x bf16   36 B   4 x bf16 + 2 x bf16   12 B
+//
+// F16S stores value / s as IEEE half, with s = max |real| of the site (one
+// scale per site and direction for W, per site and RHS for vectors); s = 0
+// encodes an all-zero site.  Stores round to nearest even.  FP64 values
+// headed for half or bf16 are rounded to FP32 first.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "tl_internal.h"
+
+namespace tl {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ float h_to_f32(uint32_t bits16) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+
+__device__ __forceinline__ uint32_t f32_to_h(float f) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) { return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16); }
+__device__ __forceinline__ uint32_t pack_h(float lo, float hi) { return f32_to_h(lo) | (f32_to_h(hi) << 16); }
+
+template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+
+template <int P> struct Fmt;
+
+// ------------------------------------------------------------------ FP64
+template <> struct Fmt<F64> {
+  using real = double;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    const double2* p = reinterpret_cast<const double2*>(b);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      double2 v = p[k * Vp + i];
+      m[2 * k] = (T)v.x;
+      m[2 * k + 1] = (T)v.y;
+    }
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    double2* p = reinterpret_cast<double2*>(b);
+#pragma unroll
+    for (int k = 0; k < 9; k++) p[k * Vp + i] = make_double2(m[2 * k], m[2 * k + 1]);
+  }
+  template <typename T>
+  __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
+    const double2* p = reinterpret_cast<const double2*>(b);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      double2 w = p[c * Vp + i];
+      v[2 * c] = (T)w.x;
+      v[2 * c + 1] = (T)w.y;
+    }
+  }
+  template <typename T>
+  __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
+    double2* p = reinterpret_cast<double2*>(b);
+#pragma unroll
+    for (int c = 0; c < 3; c++) p[c * Vp + i] = make_double2((double)v[2 * c], (double)v[2 * c + 1]);
+  }
+};
+
+// ------------------------------------------------------------------ FP32
+template <> struct Fmt<F32> {
+  using real = float;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    const float4* p = reinterpret_cast<const float4*>(b);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      float4 v = p[k * Vp + i];
+      m[4 * k] = v.x;
+      m[4 * k + 1] = v.y;
+      m[4 * k + 2] = v.z;
+      m[4 * k + 3] = v.w;
+    }
+    float2 v = reinterpret_cast<const float2*>(b + 64 * Vp)[i];
+    m[16] = v.x;
+    m[17] = v.y;
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    float4* p = reinterpret_cast<float4*>(b);
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      p[k * Vp + i] = make_float4((float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]);
+    reinterpret_cast<float2*>(b + 64 * Vp)[i] = make_float2((float)m[16], (float)m[17]);
+  }
+  template <typename T>
+  __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
+    float4 a = reinterpret_cast<const float4*>(b)[i];
+    float2 c = reinterpret_cast<const float2*>(b + 16 * Vp)[i];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y;
+  }
+  template <typename T>
+  __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
+    reinterpret_cast<float4*>(b)[i] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    reinterpret_cast<float2*>(b + 16 * Vp)[i] = make_float2((float)v[4], (float)v[5]);
+  }
+};
+
+// ------------------------------------------------------------------ F16S
+template <> struct Fmt<F16S> {
+  using real = float;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
+    uint4 p1 = reinterpret_cast<const uint4*>(b + 16 * Vp)[i];
+    uint2 p2 = reinterpret_cast<const uint2*>(b + 32 * Vp)[i];
+    const float s = __uint_as_float(p2.y);
+    const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      m[2 * k] = h_to_f32(w[k] & 0xffffu) * s;
+      m[2 * k + 1] = h_to_f32(w[k] >> 16) * s;
+    }
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < 18; k++) mx = fmax(mx, fabs(m[k]));
+    const float s = (float)mx;
+    const double inv = s > 0.0f ? 1.0 / (double)s : 0.0;
+    uint32_t w[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) w[k] = pack_h((float)(m[2 * k] * inv), (float)(m[2 * k + 1] * inv));
+    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint4*>(b + 16 * Vp)[i] = make_uint4(w[4], w[5], w[6], w[7]);
+    reinterpret_cast<uint2*>(b + 32 * Vp)[i] = make_uint2(w[8], __float_as_uint(s));
+  }
+  template <typename T>
+  __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
+    (void)Vp;
+    uint4 p = reinterpret_cast<const uint4*>(b)[i];
+    const float s = __uint_as_float(p.w);
+    v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
+    v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
+    v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
+  }
+  template <typename T>
+  __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
+    (void)Vp;
+    float f[6];
+    float mx = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      f[c] = (float)v[c];
+      mx = fmaxf(mx, fabsf(f[c]));
+    }
+    const float inv = mx > 0.0f ? 1.0f / mx : 0.0f;
+    reinterpret_cast<uint4*>(b)[i] = make_uint4(pack_h(f[0] * inv, f[1] * inv), pack_h(f[2] * inv, f[3] * inv),
+                                                pack_h(f[4] * inv, f[5] * inv), __float_as_uint(mx));
+  }
+};
+
+// ------------------------------------------------------------------ BF16
+template <> struct Fmt<BF16> {
+  using real = float;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
+    uint4 p1 = reinterpret_cast<const uint4*>(b + 16 * Vp)[i];
+    uint32_t p2 = reinterpret_cast<const uint32_t*>(b + 32 * Vp)[i];
+    const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2};
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      m[2 * k] = bf16_to_f32(w[k] & 0xffffu);
+      m[2 * k + 1] = bf16_to_f32(w[k] >> 16);
+    }
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    uint32_t w[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) w[k] = pack_bf16((float)m[2 * k], (float)m[2 * k + 1]);
+    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint4*>(b + 16 * Vp)[i] = make_uint4(w[4], w[5], w[6], w[7]);
+    reinterpret_cast<uint32_t*>(b + 32 * Vp)[i] = w[8];
+  }
+  template <typename T>
+  __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
+    uint2 p = reinterpret_cast<const uint2*>(b)[i];
+    uint32_t q = reinterpret_cast<const uint32_t*>(b + 8 * Vp)[i];
+    v[0] = bf16_to_f32(p.x & 0xffffu); v[1] = bf16_to_f32(p.x >> 16);
+    v[2] = bf16_to_f32(p.y & 0xffffu); v[3] = bf16_to_f32(p.y >> 16);
+    v[4] = bf16_to_f32(q & 0xffffu);   v[5] = bf16_to_f32(q >> 16);
+  }
+  template <typename T>
+  __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
+    reinterpret_cast<uint2*>(b)[i] = make_uint2(pack_bf16((float)v[0], (float)v[1]), pack_bf16((float)v[2], (float)v[3]));
+    reinterpret_cast<uint32_t*>(b + 8 * Vp)[i] = pack_bf16((float)v[4], (float)v[5]);
+  }
+};
+
+}  // namespace tl

@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernels (tl_kernels.hip) and the host
+// runtime (tl_runtime.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tl {
+
+// Storage precisions (same values as TL_F64 ... TL_BF16 in twolink.h).
+enum Prec : int { F64 = 0, F32 = 1, F16S = 2, BF16 = 3 };
+
+// Packed two-link field: per slot, per direction mu, per site, kWBytes[prec]
+// bytes split into planes of vector words (see tl_format.h).  Packed colour
+// vectors: per right-hand side, per site, kVBytes[prec] bytes, also in planes.
+constexpr int kWBytes[4] = {144, 72, 40, 36};
+constexpr int kVBytes[4] = {48, 24, 16, 12};
+
+// Plane length: sites per plane, rounded up so every plane starts 256-byte aligned.
+inline int64_t padded_sites(int64_t v3) { return (v3 + 63) / 64 * 64; }
+
+// A set of right-hand sides on one time slice of one lattice that share the
+// two-link loads of a smearing step, plus the geometry of its tiles.
+struct StepGroup {
+  const char* W;          // packed two-link slot of the slice (direction x block)
+  int64_t w_mu_stride;    // bytes between direction blocks (Vp * kWBytes)
+  int64_t psi_off;        // byte offset of the group's first RHS in the resident buffers
+  int64_t rhs_stride;     // bytes between consecutive RHS of the group (Vp * kVBytes)
+  int32_t Lx, Ly, Lz;
+  int32_t Vp;             // plane length (padded sites)
+  int32_t nr;             // RHS in the group
+  int32_t n_xy_tiles;     // ceil(Lx*Ly / block)
+  int32_t n_z_tiles;      // ceil(Lz / tz)
+  int32_t tile_begin;     // work-list index of the group's first tile
+};
+
+// Launch configuration of the step kernel.
+struct StepConfig {
+  int variant;   // 0: one site per thread per z plane, neighbours through the caches
+                 // 1: z-marching with a register ring for the z hops
+  int block;     // threads per workgroup (xy sites per tile)
+  int tz;        // z planes per tile
+  int grid;      // workgroups; <= 0 means one workgroup per tile
+};
+
+// psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).
+hipError_t launch_step(int prec, int width, const StepConfig& cfg, const StepGroup* groups,
+                       int n_groups, int tile_base, int n_tiles, const char* in, char* out,
+                       double alpha, double beta, hipStream_t stream);
+
+// W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1.
+hipError_t launch_build(int prec, const void* U, const int32_t L[4], int t_first, int slot_first, int n,
+                        void* W, hipStream_t stream);
+
+// Natural complex128 [rhs][V3][3] <-> packed resident field.  rhs_off[r] is
+// the byte offset of RHS r in the packed buffer (device array).
+hipError_t launch_pack(int prec, const void* nat, char* packed, const int64_t* rhs_off_dev,
+                       int n_rhs, int64_t V3, int64_t Vp, hipStream_t stream);
+hipError_t launch_unpack(int prec, const char* packed, void* nat, const int64_t* rhs_off_dev,
+                         int n_rhs, int64_t V3, int64_t Vp, hipStream_t stream);
+
+// Description of one RHS for the reductions.
+struct RedField {
+  int64_t off;      // byte offset (packed) or element offset (natural) of the RHS
+  int64_t off2;     // same for the second field of a dot product
+  int64_t V3;       // sites
+  int64_t Vp;       // plane length (packed)
+  int64_t out_off;  // first output index of this RHS (site norms)
+};
+
+// kind: 0 norm2, 1 dot, 2 site norms.  prec = -1 selects natural complex128
+// fields.  partials: device scratch of at least red_partials_doubles(n_rhs) doubles.
+int64_t red_partials_doubles(int n_rhs, int64_t max_v3);
+hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const RedField* fields_dev,
+                         int n_rhs, int64_t max_v3, double* partials, double* out, hipStream_t stream);
+
+// flag[0] = 1 if the n_bytes at a and b differ anywhere (flag must be cleared by the caller).
+hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t stream);
+
+}  // namespace tl

@@ -1,0 +1,525 @@
+// HIP kernels for gfx950: two-link build, pack/unpack, the fused smearing
+// step, FP64 reductions.
+//
+// Smearing step (eq. tlSmear with eq. tlLapl1), per right-hand side r:
+//   out_r(x) = alpha in_r(x) + beta sum_mu [W_mu(x) in_r(x+2mu^) + W_mu^dag(x-2mu^) in_r(x-2mu^)]
+// with alpha = 1 - 6 sigma/(4n) and beta = sigma/(4n), which is
+// in + (sigma/n) Lap in.  (alpha = -3/2, beta = 1/4 gives Lap itself.)
+// The RHS of one group live on the same slice and share every two-link load.
+// Accumulation order per site is fixed (x fwd, x bwd, y fwd, y bwd, z fwd,
+// z bwd, then the axpy), written with explicit fused multiply-adds, so every
+// kernel variant and tiling produces bit-identical results.
+
+#include <hip/hip_runtime.h>
+
+#include "tl_format.h"
+#include "tl_internal.h"
+
+namespace tl {
+
+namespace {
+
+constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b % 8).  Give the workgroups of one XCD a contiguous range of the work
+// list and let them sweep it together, so neighbouring tiles (which share
+// halo sites and two-links) meet in the same L2.  Correctness does not
+// depend on the dispatch order.
+struct TileSweep {
+  int first, stride, end;
+};
+
+__device__ __forceinline__ TileSweep xcd_sweep(int n_tiles) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int k = b % kXcds, j = b / kXcds;
+  const int q = G / kXcds, r = G % kXcds;
+  const int cnt = q + (k < r ? 1 : 0);                     // workgroups on this XCD
+  const int ord0 = k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q;  // their first ordinal
+  const int t0 = (int)(((int64_t)n_tiles * ord0) / G);
+  const int t1 = (int)(((int64_t)n_tiles * (ord0 + cnt)) / G);
+  return {t0 + j, cnt, t1};
+}
+
+__device__ __forceinline__ int wrap_step(int v, int d, int L) {
+  v += d;
+  while (v >= L) v -= L;
+  while (v < 0) v += L;
+  return v;
+}
+
+// acc += M v   (3x3 complex times colour vector)
+template <typename T>
+__device__ __forceinline__ void mv_acc(const T (&m)[18], const T (&v)[6], T (&acc)[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    T re = acc[2 * a], im = acc[2 * a + 1];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const T mr = m[2 * (3 * a + b)], mi = m[2 * (3 * a + b) + 1];
+      re = fma_(mr, v[2 * b], re);
+      re = fma_(-mi, v[2 * b + 1], re);
+      im = fma_(mr, v[2 * b + 1], im);
+      im = fma_(mi, v[2 * b], im);
+    }
+    acc[2 * a] = re;
+    acc[2 * a + 1] = im;
+  }
+}
+
+// acc += M^dag v
+template <typename T>
+__device__ __forceinline__ void mdv_acc(const T (&m)[18], const T (&v)[6], T (&acc)[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    T re = acc[2 * a], im = acc[2 * a + 1];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const T mr = m[2 * (3 * b + a)], mi = m[2 * (3 * b + a) + 1];
+      re = fma_(mr, v[2 * b], re);
+      re = fma_(mi, v[2 * b + 1], re);
+      im = fma_(mr, v[2 * b + 1], im);
+      im = fma_(-mi, v[2 * b], im);
+    }
+    acc[2 * a] = re;
+    acc[2 * a + 1] = im;
+  }
+}
+
+__device__ __forceinline__ int find_group(const StepGroup* __restrict__ groups, int n_groups, int tile) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ step kernels
+
+// Variant 0: each thread owns one (x, y) site of the tile and walks the tile's
+// z planes; every neighbour value comes through L1/L2.
+template <int P, int R>
+__global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  constexpr int VB = kVBytes[P];
+  (void)VB;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};    // +2 in x, y
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};  // -2 in x, y
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const char* pin = in + g.psi_off;
+    char* pout = out + g.psi_off;
+    const int nr = g.nr;
+    const int64_t rs = g.rhs_stride;
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t zp = (int64_t)wrap_step(z, 2, Lz) * LxLy;
+      const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t fwd[3] = {zo + xyp[0], zo + xyp[1], zp + xy};
+      const int64_t bwd[3] = {zo + xym[0], zo + xym[1], zm + xy};
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 3; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, fwd[mu], v);
+            mv_acc(m, v, acc[r]);
+          }
+        }
+        F::load_w(Wmu[mu], Vp, bwd[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, bwd[mu], v);
+            mdv_acc(m, v, acc[r]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        if (r < nr) {
+          real v[6], o[6];
+          F::load_v(pin + r * rs, Vp, site, v);
+#pragma unroll
+          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
+          F::store_v(pout + r * rs, Vp, site, o);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ build
+
+// W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in precision P.  One thread per site.
+template <int P>
+__global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __restrict__ U, int Lx, int Ly, int Lz,
+                                                              int t_first, int slot_first,
+                                                              char* __restrict__ W, int64_t Vp) {
+  const int slot = slot_first + (int)blockIdx.y;
+  const int t = t_first + (int)blockIdx.y;
+  const int64_t V3 = (int64_t)Lx * Ly * Lz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V3) return;
+  const int x = (int)(i % Lx);
+  const int y = (int)((i / Lx) % Ly);
+  const int z = (int)(i / ((int64_t)Lx * Ly));
+  const int64_t nb[3] = {
+      ((int64_t)z * Ly + y) * Lx + wrap_step(x, 1, Lx),
+      ((int64_t)z * Ly + wrap_step(y, 1, Ly)) * Lx + x,
+      ((int64_t)wrap_step(z, 1, Lz) * Ly + y) * Lx + x};
+  const int64_t base = (int64_t)t * V3;
+  constexpr int WB = kWBytes[P];
+#pragma unroll
+  for (int mu = 0; mu < 3; mu++) {
+    const double2* A = U + ((base + i) * 4 + mu) * 9;
+    const double2* B = U + ((base + nb[mu]) * 4 + mu) * 9;
+    double2 a[9], b[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) a[k] = A[k];
+#pragma unroll
+    for (int k = 0; k < 9; k++) b[k] = B[k];
+    double c[18];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+      for (int s = 0; s < 3; s++) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          const double2 p = a[3 * r + k], q = b[3 * k + s];
+          re = fma_(p.x, q.x, re);
+          re = fma_(-p.y, q.y, re);
+          im = fma_(p.x, q.y, im);
+          im = fma_(p.y, q.x, im);
+        }
+        c[2 * (3 * r + s)] = re;
+        c[2 * (3 * r + s) + 1] = im;
+      }
+    Fmt<P>::store_w(W + ((int64_t)slot * 3 + mu) * Vp * WB, Vp, i, c);
+  }
+}
+
+// ------------------------------------------------------------------ pack / unpack
+
+template <int P>
+__global__ __launch_bounds__(256) void pack_kernel(const double2* __restrict__ nat, char* __restrict__ packed,
+                                                   const int64_t* __restrict__ rhs_off, int64_t V3, int64_t Vp) {
+  const int r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V3) return;
+  const double2* s = nat + ((int64_t)r * V3 + i) * 3;
+  double v[6];
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const double2 w = s[c];
+    v[2 * c] = w.x;
+    v[2 * c + 1] = w.y;
+  }
+  Fmt<P>::store_v(packed + rhs_off[r], Vp, i, v);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void unpack_kernel(const char* __restrict__ packed, double2* __restrict__ nat,
+                                                     const int64_t* __restrict__ rhs_off, int64_t V3, int64_t Vp) {
+  const int r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V3) return;
+  double v[6];
+  Fmt<P>::load_v(packed + rhs_off[r], Vp, i, v);
+  double2* d = nat + ((int64_t)r * V3 + i) * 3;
+#pragma unroll
+  for (int c = 0; c < 3; c++) d[c] = make_double2(v[2 * c], v[2 * c + 1]);
+}
+
+// ------------------------------------------------------------------ reductions
+
+constexpr int kRedBlock = 256;
+constexpr int kRedSitesPerBlock = 4096;
+
+// Natural complex128 vectors: [..][site][3].
+struct NatLoad {
+  __device__ static void load(const char* b, int64_t off, int64_t Vp, int64_t i, double (&v)[6]) {
+    (void)Vp;
+    const double2* p = reinterpret_cast<const double2*>(b) + off + i * 3;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const double2 w = p[c];
+      v[2 * c] = w.x;
+      v[2 * c + 1] = w.y;
+    }
+  }
+};
+
+template <int P>
+struct PackedLoad {
+  __device__ static void load(const char* b, int64_t off, int64_t Vp, int64_t i, double (&v)[6]) {
+    Fmt<P>::load_v(b + off, Vp, i, v);
+  }
+};
+
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  // wave64 butterfly, then the waves' partial sums in wave order
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) s += lds[w];
+  __syncthreads();
+  return s;
+}
+
+// partials[(r * nb + b) * 2 + {0,1}]: block b of RHS r.  Fixed site-to-block
+// and in-block orders make the result reproducible run to run.
+template <class LD>
+__global__ __launch_bounds__(kRedBlock) void reduce_partial_kernel(int kind, const char* __restrict__ a,
+                                                                   const char* __restrict__ b,
+                                                                   const RedField* __restrict__ f,
+                                                                   double* __restrict__ partials) {
+  __shared__ double lds[kRedBlock / 64];
+  const int r = blockIdx.y;
+  const int nb = gridDim.x;
+  const RedField fr = f[r];
+  const int64_t s0 = (int64_t)blockIdx.x * kRedSitesPerBlock;
+  const int64_t s1 = min(s0 + (int64_t)kRedSitesPerBlock, fr.V3);
+  double re = 0.0, im = 0.0;
+  for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+    double v[6];
+    LD::load(a, fr.off, fr.Vp, i, v);
+    if (kind == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; c++) re = fma_(v[c], v[c], re);
+    } else {
+      double u[6];
+      LD::load(b, fr.off2, fr.Vp, i, u);   // <u, v> = sum conj(u) v
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        re = fma_(u[2 * c], v[2 * c], re);
+        re = fma_(u[2 * c + 1], v[2 * c + 1], re);
+        im = fma_(u[2 * c], v[2 * c + 1], im);
+        im = fma_(-u[2 * c + 1], v[2 * c], im);
+      }
+    }
+  }
+  re = block_sum(re, lds);
+  if (kind == 1) im = block_sum(im, lds);
+  if (threadIdx.x == 0) {
+    partials[((int64_t)r * nb + blockIdx.x) * 2] = re;
+    partials[((int64_t)r * nb + blockIdx.x) * 2 + 1] = im;
+  }
+}
+
+__global__ void reduce_finish_kernel(int kind, const double* __restrict__ partials, int nb, int n_rhs,
+                                     double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rhs) return;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < nb; k++) {
+    re += partials[((int64_t)r * nb + k) * 2];
+    im += partials[((int64_t)r * nb + k) * 2 + 1];
+  }
+  if (kind == 0) {
+    out[r] = re;
+  } else {
+    out[2 * r] = re;
+    out[2 * r + 1] = im;
+  }
+}
+
+template <class LD>
+__global__ __launch_bounds__(kRedBlock) void site_norm_kernel(const char* __restrict__ a, const RedField* __restrict__ f,
+                                                              double* __restrict__ out) {
+  const int r = blockIdx.y;
+  const RedField fr = f[r];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= fr.V3) return;
+  double v[6];
+  LD::load(a, fr.off, fr.Vp, i, v);
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; c++) s = fma_(v[c], v[c], s);
+  out[fr.out_off + i] = sqrt(s);
+}
+
+__global__ void compare_kernel(const uint4* __restrict__ a, const uint4* __restrict__ b, int64_t n16,
+                               const unsigned char* __restrict__ ta, const unsigned char* __restrict__ tb,
+                               int64_t ntail, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool diff = false;
+  for (int64_t k = i; k < n16; k += stride) {
+    const uint4 x = a[k], y = b[k];
+    diff |= (x.x != y.x) | (x.y != y.y) | (x.z != y.z) | (x.w != y.w);
+  }
+  for (int64_t k = i; k < ntail; k += stride) diff |= ta[k] != tb[k];
+  if (diff) *flag = 1;
+}
+
+template <int P, int R>
+hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+  using real = typename Fmt<P>::real;
+  const int grid = cfg.grid > 0 ? std::min(cfg.grid, n_tiles) : n_tiles;
+  if (cfg.variant == 0) {
+    step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                 (real)alpha, (real)beta);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_step_p(int width, const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+  switch (width) {
+    case 1: return launch_step_t<P, 1>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    case 2: return launch_step_t<P, 2>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    case 3: return launch_step_t<P, 3>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    case 4: return launch_step_t<P, 4>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step(int prec, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
+                       int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
+                       hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 != 0 || cfg.tz < 1) return hipErrorInvalidValue;
+  switch (prec) {
+    case F64: return launch_step_p<F64>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
+    case F32: return launch_step_p<F32>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
+    case F16S: return launch_step_p<F16S>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
+    case BF16: return launch_step_p<BF16>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_build(int prec, const void* U, const int32_t L[4], int t_first, int slot_first, int n_slices,
+                        void* W, hipStream_t s) {
+  const int64_t V3 = (int64_t)L[0] * L[1] * L[2];
+  const int64_t Vp = padded_sites(V3);
+  if (n_slices <= 0 || V3 <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((V3 + 255) / 256), (unsigned)n_slices);
+  const double2* u = static_cast<const double2*>(U);
+  char* w = static_cast<char*>(W);
+  switch (prec) {
+    case F64: build_twolinks_kernel<F64><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp); break;
+    case F32: build_twolinks_kernel<F32><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp); break;
+    case F16S: build_twolinks_kernel<F16S><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp); break;
+    case BF16: build_twolinks_kernel<BF16><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, const void* nat, char* packed, const int64_t* rhs_off, int n_rhs, int64_t V3,
+                       int64_t Vp, hipStream_t s) {
+  if (n_rhs <= 0 || V3 <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((V3 + 255) / 256), (unsigned)n_rhs);
+  const double2* n = static_cast<const double2*>(nat);
+  switch (prec) {
+    case F64: pack_kernel<F64><<<grid, 256, 0, s>>>(n, packed, rhs_off, V3, Vp); break;
+    case F32: pack_kernel<F32><<<grid, 256, 0, s>>>(n, packed, rhs_off, V3, Vp); break;
+    case F16S: pack_kernel<F16S><<<grid, 256, 0, s>>>(n, packed, rhs_off, V3, Vp); break;
+    case BF16: pack_kernel<BF16><<<grid, 256, 0, s>>>(n, packed, rhs_off, V3, Vp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(int prec, const char* packed, void* nat, const int64_t* rhs_off, int n_rhs, int64_t V3,
+                         int64_t Vp, hipStream_t s) {
+  if (n_rhs <= 0 || V3 <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((V3 + 255) / 256), (unsigned)n_rhs);
+  double2* n = static_cast<double2*>(nat);
+  switch (prec) {
+    case F64: unpack_kernel<F64><<<grid, 256, 0, s>>>(packed, n, rhs_off, V3, Vp); break;
+    case F32: unpack_kernel<F32><<<grid, 256, 0, s>>>(packed, n, rhs_off, V3, Vp); break;
+    case F16S: unpack_kernel<F16S><<<grid, 256, 0, s>>>(packed, n, rhs_off, V3, Vp); break;
+    case BF16: unpack_kernel<BF16><<<grid, 256, 0, s>>>(packed, n, rhs_off, V3, Vp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int64_t red_partials_doubles(int n_rhs, int64_t max_v3) {
+  const int64_t nb = std::max<int64_t>(1, (max_v3 + kRedSitesPerBlock - 1) / kRedSitesPerBlock);
+  return 2 * nb * std::max(n_rhs, 1);
+}
+
+hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const RedField* f, int n_rhs,
+                         int64_t max_v3, double* partials, double* out, hipStream_t s) {
+  if (n_rhs <= 0 || max_v3 <= 0) return hipSuccess;
+  if (kind == 2) {
+    const dim3 grid((unsigned)((max_v3 + kRedBlock - 1) / kRedBlock), (unsigned)n_rhs);
+    switch (prec) {
+      case -1: site_norm_kernel<NatLoad><<<grid, kRedBlock, 0, s>>>(a, f, out); break;
+      case F64: site_norm_kernel<PackedLoad<F64>><<<grid, kRedBlock, 0, s>>>(a, f, out); break;
+      case F32: site_norm_kernel<PackedLoad<F32>><<<grid, kRedBlock, 0, s>>>(a, f, out); break;
+      case F16S: site_norm_kernel<PackedLoad<F16S>><<<grid, kRedBlock, 0, s>>>(a, f, out); break;
+      case BF16: site_norm_kernel<PackedLoad<BF16>><<<grid, kRedBlock, 0, s>>>(a, f, out); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  const int nb = (int)((max_v3 + kRedSitesPerBlock - 1) / kRedSitesPerBlock);
+  const dim3 grid((unsigned)nb, (unsigned)n_rhs);
+  switch (prec) {
+    case -1: reduce_partial_kernel<NatLoad><<<grid, kRedBlock, 0, s>>>(kind, a, b, f, partials); break;
+    case F64: reduce_partial_kernel<PackedLoad<F64>><<<grid, kRedBlock, 0, s>>>(kind, a, b, f, partials); break;
+    case F32: reduce_partial_kernel<PackedLoad<F32>><<<grid, kRedBlock, 0, s>>>(kind, a, b, f, partials); break;
+    case F16S: reduce_partial_kernel<PackedLoad<F16S>><<<grid, kRedBlock, 0, s>>>(kind, a, b, f, partials); break;
+    case BF16: reduce_partial_kernel<PackedLoad<BF16>><<<grid, kRedBlock, 0, s>>>(kind, a, b, f, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  reduce_finish_kernel<<<(n_rhs + 63) / 64, 64, 0, s>>>(kind, partials, nb, n_rhs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t s) {
+  const int64_t n16 = n_bytes / 16;
+  const int64_t tail = n_bytes - n16 * 16;
+  compare_kernel<<<1024, 256, 0, s>>>(reinterpret_cast<const uint4*>(a), reinterpret_cast<const uint4*>(b), n16,
+                                      reinterpret_cast<const unsigned char*>(a) + n16 * 16,
+                                      reinterpret_cast<const unsigned char*>(b) + n16 * 16, tail, flag);
+  return hipGetLastError();
+}
+
+}  // namespace tl

@@ -1,0 +1,891 @@
+// Host runtime behind the C ABI of twolink.h: contexts, argument validation,
+// resident plans (packing, work lists, tuning, HIP graph capture), reductions.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tl_internal.h"
+#include "twolink.h"
+
+using tl::StepConfig;
+using tl::StepGroup;
+
+static_assert(TL_F64 == tl::F64 && TL_F32 == tl::F32 && TL_F16S == tl::F16S && TL_BF16 == tl::BF16,
+              "precision codes");
+
+struct tl_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_cu = 0;
+  std::string arch;
+  bool log = false;
+  bool fault_alloc = false;   // TL_FAULT=alloc: internal allocations report failure
+  bool fault_launch = false;  // TL_FAULT=launch: launches report failure without running
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::map<std::string, StepConfig> tune;  // tuned step configurations by workload key
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int vfail(tl_ctx* c, int code, const char* fmt, va_list ap) {
+  char buf[1024];
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  if (c) c->err = buf; else g_create_err = buf;
+  return code;
+}
+
+int fail(tl_ctx* c, int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vfail(c, code, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail((ctx), TL_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TL_TRY(expr)            \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != TL_OK) return rc_; \
+  } while (0)
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool valid_prec(int p) { return p >= TL_F64 && p <= TL_BF16; }
+
+int check_geom(tl_ctx* c, const tl_geom* g) {
+  if (!g) return fail(c, TL_ERR_ARG, "geometry is NULL");
+  for (int d = 0; d < 4; d++)
+    if (g->L[d] < 1 || g->L[d] > 4096)
+      return fail(c, TL_ERR_SHAPE, "extent L[%d] = %d outside [1, 4096]", d, g->L[d]);
+  const int64_t v3 = (int64_t)g->L[0] * g->L[1] * g->L[2];
+  if (v3 > (int64_t(1) << 27)) return fail(c, TL_ERR_SHAPE, "slice volume %lld exceeds 2^27 sites", (long long)v3);
+  return TL_OK;
+}
+
+int64_t vol3(const tl_geom& g) { return (int64_t)g.L[0] * g.L[1] * g.L[2]; }
+
+int need_device(tl_ctx* c) {
+  if (c->device < 0) return fail(c, TL_ERR_DEVICE, "host-only context (created with device -1) cannot run device work");
+  return TL_OK;
+}
+
+int dev_alloc(tl_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (c->fault_alloc) return fail(c, TL_ERR_NOMEM, "device allocation of %zu bytes failed (TL_FAULT=alloc)", bytes);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(c, TL_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return TL_OK;
+}
+
+// Queue one library launch; TL_FAULT=launch makes it fail before anything is queued.
+template <class F>
+int launch(tl_ctx* c, const char* what, F&& f) {
+  if (c->fault_launch) return fail(c, TL_ERR_HIP, "%s launch failed (TL_FAULT=launch)", what);
+  const hipError_t e = f();
+  if (e != hipSuccess) return fail(c, TL_ERR_HIP, "%s launch: %s", what, hipGetErrorString(e));
+  return TL_OK;
+}
+
+// Context scratch: grows on demand; stream-ordered reuse is safe because every
+// user queues on the context stream and waits before overwriting host tables.
+int ctx_scratch(tl_ctx* c, size_t bytes, char** out) {
+  if (bytes > c->scratch_bytes) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->scratch) HIP_TRY(c, hipFree(c->scratch));
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    void* p = nullptr;
+    TL_TRY(dev_alloc(c, &p, bytes));
+    c->scratch = p;
+    c->scratch_bytes = bytes;
+  }
+  *out = static_cast<char*>(c->scratch);
+  return TL_OK;
+}
+
+// Synchronous upload of a small host table onto the context stream.
+int upload(tl_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return TL_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TL_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Slot of slice t in a two-link field built for w_slices (NULL = all slices).
+int slot_of(const tl_geom& g, const int32_t* w_slices, int n_w, int t) {
+  if (t < 0 || t >= g.L[3]) return -1;
+  if (!w_slices) return t;
+  for (int j = 0; j < n_w; j++)
+    if (w_slices[j] == t) return j;
+  return -1;
+}
+
+int check_wslices(tl_ctx* c, const tl_geom& g, const int32_t* w_slices, int n_w) {
+  if (!w_slices) return TL_OK;
+  if (n_w < 1 || n_w > g.L[3]) return fail(c, TL_ERR_ARG, "n_w_slices = %d outside [1, Lt=%d]", n_w, g.L[3]);
+  for (int j = 0; j < n_w; j++)
+    if (w_slices[j] < 0 || w_slices[j] >= g.L[3])
+      return fail(c, TL_ERR_SHAPE, "w_slices[%d] = %d outside [0, %d)", j, w_slices[j], g.L[3]);
+  return TL_OK;
+}
+
+// Coefficients of one smearing step: out = alpha in + beta sum_hops.
+void step_coeffs(int n_steps, double sigma, double* alpha, double* beta) {
+  const double s = sigma / (double)n_steps;
+  *alpha = 1.0 - 1.5 * s;
+  *beta = 0.25 * s;
+}
+
+}  // namespace
+
+// ====================================================================== plans
+
+struct tl_plan {
+  tl_ctx* ctx = nullptr;
+  int prec = 0, n_steps = 0;
+  double sigma = 0.0, alpha = 1.0, beta = 0.0;
+  unsigned flags = 0;
+
+  struct JobCopy {
+    tl_job job;
+    std::vector<int32_t> t_of_rhs, w_slices;
+    int64_t V3 = 0, Vp = 0;
+    std::vector<int> res_index;   // job RHS r -> resident RHS index
+  };
+  std::vector<JobCopy> jobs;
+
+  struct Res {
+    int job, r, slot;
+    int64_t off;                  // byte offset in each resident buffer
+  };
+  std::vector<Res> res;           // resident order: grouped by (job, slot)
+
+  struct Group {
+    int job, slot, first, nr;     // resident RHS [first, first + nr)
+  };
+  std::vector<Group> groups;
+  int width = 1;
+
+  size_t buf_bytes = 0;
+  char* buf[2] = {nullptr, nullptr};
+  int cur = 0;
+
+  // device tables: step groups, per-job pack offsets, reduction fields, partials
+  char* tables = nullptr;
+  StepGroup* groups_dev = nullptr;
+  int64_t* packoff_dev = nullptr;
+  std::vector<int64_t> packoff_first;   // index of job j's first entry in packoff_dev
+  tl::RedField* red_dev = nullptr;
+  double* partials = nullptr;
+  int64_t max_v3 = 0;
+
+  std::vector<StepGroup> groups_host;
+  int n_tiles = 0;
+  StepConfig cfg{0, 256, 4, 0};
+  bool ready = false;                   // tuning done (or not requested) and table uploaded
+
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  tl_plan_info info{};
+};
+
+namespace {
+
+// Work list of a plan for one step configuration.
+int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>* out) {
+  out->clear();
+  int tiles = 0;
+  for (const auto& gr : p->groups) {
+    const auto& jc = p->jobs[gr.job];
+    const tl_geom& g = jc.job.g;
+    StepGroup s{};
+    const int64_t wslot = (int64_t)gr.slot * 3 * jc.Vp * tl::kWBytes[p->prec];
+    s.W = static_cast<const char*>(jc.job.W) + wslot;
+    s.w_mu_stride = jc.Vp * tl::kWBytes[p->prec];
+    s.psi_off = p->res[gr.first].off;
+    s.rhs_stride = gr.nr > 1 ? p->res[gr.first + 1].off - p->res[gr.first].off : 0;
+    s.Lx = g.L[0];
+    s.Ly = g.L[1];
+    s.Lz = g.L[2];
+    s.Vp = (int32_t)jc.Vp;
+    s.nr = gr.nr;
+    s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
+    s.n_z_tiles = (g.L[2] + cfg.tz - 1) / cfg.tz;
+    s.tile_begin = tiles;
+    const int64_t nt = (int64_t)s.n_xy_tiles * s.n_z_tiles;
+    if (tiles + nt > (int64_t)1 << 30) return TL_ERR_UNSUPPORTED;
+    tiles += (int)nt;
+    out->push_back(s);
+  }
+  return TL_OK;
+}
+
+int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
+  std::vector<StepGroup> gs;
+  if (make_groups(p, cfg, &gs) != TL_OK) return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list too long");
+  TL_TRY(upload(p->ctx, p->groups_dev, gs.data(), gs.size() * sizeof(StepGroup)));
+  p->groups_host = gs;
+  p->n_tiles = gs.empty() ? 0 : gs.back().tile_begin + gs.back().n_xy_tiles * gs.back().n_z_tiles;
+  return TL_OK;
+}
+
+// One step over every group (batched) or over one group (plain mode, g >= 0).
+int plan_step(tl_plan* p, hipStream_t s, int parity, int g) {
+  tl_ctx* c = p->ctx;
+  int base = 0, n = p->n_tiles;
+  if (g >= 0) {
+    base = p->groups_host[g].tile_begin;
+    n = p->groups_host[g].n_xy_tiles * p->groups_host[g].n_z_tiles;
+  }
+  return launch(c, "smearing step", [&] {
+    return tl::launch_step(p->prec, p->width, p->cfg, p->groups_dev, (int)p->groups_host.size(), base, n,
+                           p->buf[parity], p->buf[parity ^ 1], p->alpha, p->beta, s);
+  });
+}
+
+// Queue the n steps starting from buffer `parity` on stream s.
+int plan_enqueue(tl_plan* p, hipStream_t s, int parity) {
+  if (p->flags & TL_PLAIN) {
+    for (int g = 0; g < (int)p->groups_host.size(); g++) {
+      int q = parity;
+      for (int k = 0; k < p->n_steps; k++) {
+        TL_TRY(plan_step(p, s, q, g));
+        q ^= 1;
+      }
+    }
+  } else {
+    int q = parity;
+    for (int k = 0; k < p->n_steps; k++) {
+      TL_TRY(plan_step(p, s, q, -1));
+      q ^= 1;
+    }
+  }
+  return TL_OK;
+}
+
+std::string tune_key(const tl_plan* p) {
+  std::string k = p->ctx->arch + "|p" + std::to_string(p->prec) + "|w" + std::to_string(p->width) +
+                  ((p->flags & TL_PLAIN) ? "|plain" : "|batch");
+  for (const auto& g : p->groups) {
+    const tl_geom& ge = p->jobs[g.job].job.g;
+    k += "|" + std::to_string(ge.L[0]) + "x" + std::to_string(ge.L[1]) + "x" + std::to_string(ge.L[2]) + ":" +
+         std::to_string(g.nr);
+  }
+  return k;
+}
+
+// Time every candidate tiling on the plan's own data (buffer cur -> cur^1,
+// which leaves the input untouched), require each candidate's output to be
+// bit-identical to the first candidate's, keep the fastest.
+int plan_autotune(tl_plan* p) {
+  tl_ctx* c = p->ctx;
+  const std::string key = tune_key(p);
+  auto hit = c->tune.find(key);
+  if (hit != c->tune.end()) {
+    p->cfg = hit->second;
+    return plan_upload_groups(p, p->cfg);
+  }
+  std::vector<StepConfig> cands;
+  const int cu = std::max(c->n_cu, 1);
+  for (int block : {256, 128, 64})
+    for (int tz : {1, 2, 4, 8, 16})
+      for (int occ : {0, 4, 8, 16}) cands.push_back({0, block, tz, occ ? occ * cu : 0});
+  void* ref = nullptr;
+  void* flag_mem = nullptr;
+  TL_TRY(dev_alloc(c, &ref, p->buf_bytes));
+  int rc = dev_alloc(c, &flag_mem, 256);
+  if (rc != TL_OK) {
+    (void)hipFree(ref);
+    return rc;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  StepConfig best_cfg = cands[0];
+  const int reps = 5;
+  for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
+    p->cfg = cands[ci];
+    rc = plan_upload_groups(p, p->cfg);
+    if (rc != TL_OK) break;
+    const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
+    for (int w = 0; w < 2 && rc == TL_OK; w++) rc = plan_step(p, c->stream, p->cur, g_lim);
+    if (rc != TL_OK) break;
+    (void)hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && rc == TL_OK; k++) rc = plan_step(p, c->stream, p->cur, g_lim);
+    (void)hipEventRecord(e1, c->stream);
+    if (rc != TL_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(c, TL_ERR_HIP, "autotune timing failed");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    bool same = true;
+    if (ci == 0) {
+      if (hipMemcpyAsync(ref, p->buf[p->cur ^ 1], p->buf_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        rc = fail(c, TL_ERR_HIP, "autotune reference copy failed");
+    } else {
+      int one = 0;
+      (void)hipMemsetAsync(flag_mem, 0, sizeof(int), c->stream);
+      (void)tl::launch_compare(static_cast<const char*>(ref), p->buf[p->cur ^ 1], (int64_t)p->buf_bytes,
+                               static_cast<int*>(flag_mem), c->stream);
+      (void)hipMemcpyAsync(&one, flag_mem, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+      (void)hipStreamSynchronize(c->stream);
+      same = one == 0;
+    }
+    if (c->log)
+      fprintf(stderr, "[twolink] tune %s block=%d tz=%d grid=%d: %.4f ms/step%s\n", key.c_str(), p->cfg.block,
+              p->cfg.tz, p->cfg.grid, ms / reps, same ? "" : "  OUTPUT DIFFERS - rejected");
+    if (same && ms < best) {
+      best = ms;
+      best_cfg = p->cfg;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(ref);
+  (void)hipFree(flag_mem);
+  if (rc != TL_OK) return rc;
+  p->cfg = best_cfg;
+  c->tune[key] = best_cfg;
+  return plan_upload_groups(p, p->cfg);
+}
+
+int plan_prepare(tl_plan* p) {
+  if (p->ready) return TL_OK;
+  if ((p->flags & TL_AUTOTUNE) && p->n_steps > 0) {
+    TL_TRY(plan_autotune(p));
+  }
+  p->ready = true;
+  return TL_OK;
+}
+
+int plan_capture(tl_plan* p, int parity) {
+  tl_ctx* c = p->ctx;
+  if (p->graph[parity]) return TL_OK;
+  hipStream_t cs = nullptr;
+  HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  int rc = TL_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(c, TL_ERR_HIP, "hipStreamBeginCapture failed");
+  } else {
+    rc = plan_enqueue(p, cs, parity);
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc == TL_OK && e != hipSuccess) rc = fail(c, TL_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  if (rc == TL_OK) {
+    hipError_t e = hipGraphInstantiate(&p->graph[parity], graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail(c, TL_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+void plan_free(tl_plan* p) {
+  if (!p) return;
+  if (p->ctx && p->ctx->device >= 0) {
+    DeviceGuard dg(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    for (auto& g : p->graph)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (auto& b : p->buf)
+      if (b) (void)hipFree(b);
+    if (p->tables) (void)hipFree(p->tables);
+  }
+  delete p;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+int tl_version(void) { return 10000; }
+
+int tl_create(tl_ctx** out, int device, void* stream) {
+  if (!out) return fail(nullptr, TL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  tl_ctx* c = new (std::nothrow) tl_ctx();
+  if (!c) return fail(nullptr, TL_ERR_NOMEM, "host allocation failed");
+  const char* lg = getenv("TL_LOG");
+  c->log = lg && lg[0] == '1';
+  const char* fl = getenv("TL_FAULT");
+  if (fl) {
+    c->fault_alloc = strcmp(fl, "alloc") == 0;
+    c->fault_launch = strcmp(fl, "launch") == 0;
+  }
+  if (device == -1) {
+    c->device = -1;
+    *out = c;
+    return TL_OK;
+  }
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n) {
+    delete c;
+    return fail(nullptr, TL_ERR_DEVICE, "device %d not available (%d devices%s%s)", device, e == hipSuccess ? n : 0,
+                e == hipSuccess ? "" : ": ", e == hipSuccess ? "" : hipGetErrorString(e));
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, TL_ERR_DEVICE, "hipGetDeviceProperties(%d) failed", device);
+  }
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->n_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  *out = c;
+  return TL_OK;
+}
+
+int tl_destroy(tl_ctx* c) {
+  if (!c) return TL_ERR_ARG;
+  if (c->device >= 0) {
+    DeviceGuard dg(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->scratch) (void)hipFree(c->scratch);
+  }
+  delete c;
+  return TL_OK;
+}
+
+int tl_set_stream(tl_ctx* c, void* stream) {
+  if (!c) return TL_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(stream);
+  return TL_OK;
+}
+
+int tl_sync(tl_ctx* c) {
+  if (!c) return TL_ERR_ARG;
+  TL_TRY(need_device(c));
+  DeviceGuard dg(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipGetLastError());
+  return TL_OK;
+}
+
+const char* tl_last_error(const tl_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int tl_check_geom(const tl_geom* g) {
+  tl_ctx tmp;
+  return check_geom(&tmp, g);
+}
+
+size_t tl_twolinks_bytes(const tl_geom* g, int prec, int n_slices) {
+  if (tl_check_geom(g) != TL_OK || !valid_prec(prec) || n_slices < 0 || n_slices > g->L[3]) return 0;
+  return (size_t)n_slices * 3 * (size_t)tl::padded_sites(vol3(*g)) * tl::kWBytes[prec];
+}
+
+int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
+                      void* W) {
+  if (!c) return TL_ERR_ARG;
+  TL_TRY(check_geom(c, g));
+  if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+  if (!U || !W) return fail(c, TL_ERR_ARG, "U and W must be non-NULL device pointers");
+  if (!slices) {
+    if (n_slices != 0 && n_slices != g->L[3])
+      return fail(c, TL_ERR_ARG, "slices is NULL but n_slices = %d (expected 0 or Lt = %d)", n_slices, g->L[3]);
+    n_slices = g->L[3];
+  } else {
+    if (n_slices < 1 || n_slices > g->L[3])
+      return fail(c, TL_ERR_ARG, "n_slices = %d outside [1, Lt=%d]", n_slices, g->L[3]);
+    std::vector<char> seen(g->L[3], 0);
+    for (int j = 0; j < n_slices; j++) {
+      if (slices[j] < 0 || slices[j] >= g->L[3])
+        return fail(c, TL_ERR_SHAPE, "slices[%d] = %d outside [0, %d)", j, slices[j], g->L[3]);
+      if (seen[slices[j]]++) return fail(c, TL_ERR_ARG, "slice %d listed twice", slices[j]);
+    }
+  }
+  TL_TRY(need_device(c));
+  DeviceGuard dg(c->device);
+  if (!slices) return launch(c, "two-link build", [&] { return tl::launch_build(prec, U, g->L, 0, 0, n_slices, W, c->stream); });
+  // runs of consecutive slices share a launch
+  int j = 0;
+  while (j < n_slices) {
+    int k = j + 1;
+    while (k < n_slices && slices[k] == slices[k - 1] + 1) k++;
+    TL_TRY(launch(c, "two-link build", [&] { return tl::launch_build(prec, U, g->L, slices[j], j, k - j, W, c->stream); }));
+    j = k;
+  }
+  return TL_OK;
+}
+
+int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_slices, int n_w_slices, int prec,
+                 int t, const void* in, void* out) {
+  if (!c) return TL_ERR_ARG;
+  TL_TRY(check_geom(c, g));
+  if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+  if (!W || !in || !out) return fail(c, TL_ERR_ARG, "W, in and out must be non-NULL device pointers");
+  TL_TRY(check_wslices(c, *g, w_slices, n_w_slices));
+  const int slot = slot_of(*g, w_slices, n_w_slices, t);
+  if (slot < 0) return fail(c, TL_ERR_SHAPE, "slice t = %d is not in the two-link field", t);
+  const int64_t V3 = vol3(*g), Vp = tl::padded_sites(V3);
+  const size_t nat_bytes = (size_t)V3 * 48;
+  const char* a = static_cast<const char*>(in);
+  const char* b = static_cast<const char*>(out);
+  if (a < b + nat_bytes && b < a + nat_bytes) return fail(c, TL_ERR_ARG, "in and out overlap");
+  TL_TRY(need_device(c));
+  DeviceGuard dg(c->device);
+  const size_t fb = align256((size_t)Vp * tl::kVBytes[prec]);
+  char* s = nullptr;
+  TL_TRY(ctx_scratch(c, 1024 + 2 * fb, &s));
+  StepGroup sg{};
+  StepConfig cfg{0, 256, 4, 0};
+  sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[prec];
+  sg.w_mu_stride = Vp * tl::kWBytes[prec];
+  sg.psi_off = 0;
+  sg.rhs_stride = 0;
+  sg.Lx = g->L[0];
+  sg.Ly = g->L[1];
+  sg.Lz = g->L[2];
+  sg.Vp = (int32_t)Vp;
+  sg.nr = 1;
+  sg.n_xy_tiles = (int32_t)(((int64_t)g->L[0] * g->L[1] + cfg.block - 1) / cfg.block);
+  sg.n_z_tiles = (g->L[2] + cfg.tz - 1) / cfg.tz;
+  sg.tile_begin = 0;
+  struct {
+    StepGroup g;
+    int64_t off0;
+  } tab{sg, 0};
+  TL_TRY(upload(c, s, &tab, sizeof tab));
+  const StepGroup* gdev = reinterpret_cast<const StepGroup*>(s);
+  const int64_t* offdev = reinterpret_cast<const int64_t*>(s + offsetof(decltype(tab), off0));
+  char* A = s + 1024;
+  char* B = A + fb;
+  TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(prec, in, A, offdev, 1, V3, Vp, c->stream); }));
+  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(prec, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, -1.5, 0.25,
+                                      c->stream); }));
+  return launch(c, "unpack", [&] { return tl::launch_unpack(prec, B, out, offdev, 1, V3, Vp, c->stream); });
+}
+
+int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags,
+                   tl_plan** out) {
+  if (!c) return TL_ERR_ARG;
+  if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!jobs || n_jobs < 1) return fail(c, TL_ERR_ARG, "need at least one job");
+  if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+  if (flags & ~(unsigned)(TL_PLAIN | TL_GRAPH | TL_AUTOTUNE)) return fail(c, TL_ERR_ARG, "unknown flag bits 0x%x", flags);
+  if ((flags & TL_PLAIN) && (flags & TL_GRAPH)) return fail(c, TL_ERR_ARG, "TL_PLAIN runs eager launches; it excludes TL_GRAPH");
+  if (n_steps < 0) return fail(c, TL_ERR_ARG, "n_steps = %d is negative", n_steps);
+  if (!std::isfinite(sigma)) return fail(c, TL_ERR_ARG, "sigma is not finite");
+  if (n_steps > 0) {
+    const double s = sigma / n_steps;
+    if (s < 0.0 || s > 2.0 / 3.0) return fail(c, TL_ERR_ARG, "sigma/n = %g outside [0, 2/3]", s);
+  }
+  for (int j = 0; j < n_jobs; j++) {
+    const tl_job& jb = jobs[j];
+    TL_TRY(check_geom(c, &jb.g));
+    if (!jb.W || !jb.psi) return fail(c, TL_ERR_ARG, "job %d: W and psi must be non-NULL", j);
+    if (jb.n_rhs < 1 || !jb.t_of_rhs) return fail(c, TL_ERR_ARG, "job %d: needs n_rhs >= 1 and t_of_rhs", j);
+    TL_TRY(check_wslices(c, jb.g, jb.w_slices, jb.n_w_slices));
+    for (int r = 0; r < jb.n_rhs; r++)
+      if (slot_of(jb.g, jb.w_slices, jb.n_w_slices, jb.t_of_rhs[r]) < 0)
+        return fail(c, TL_ERR_SHAPE, "job %d RHS %d: slice %d not in the two-link field", j, r, jb.t_of_rhs[r]);
+  }
+  TL_TRY(need_device(c));
+  DeviceGuard dg(c->device);
+
+  tl_plan* p = new (std::nothrow) tl_plan();
+  if (!p) return fail(c, TL_ERR_NOMEM, "host allocation failed");
+  p->ctx = c;
+  p->prec = prec;
+  p->n_steps = n_steps;
+  p->sigma = sigma;
+  p->flags = flags;
+  if (n_steps > 0) step_coeffs(n_steps, sigma, &p->alpha, &p->beta);
+  const int max_width = (flags & TL_PLAIN) ? 1 : 4;
+
+  // resident order: per job, per slot (in slice order), RHS in job order;
+  // groups of up to max_width RHS, balanced within a slot.
+  size_t off = 0;
+  for (int j = 0; j < n_jobs; j++) {
+    tl_plan::JobCopy jc;
+    jc.job = jobs[j];
+    jc.t_of_rhs.assign(jobs[j].t_of_rhs, jobs[j].t_of_rhs + jobs[j].n_rhs);
+    if (jobs[j].w_slices) jc.w_slices.assign(jobs[j].w_slices, jobs[j].w_slices + jobs[j].n_w_slices);
+    jc.job.t_of_rhs = jc.t_of_rhs.data();
+    jc.job.w_slices = jobs[j].w_slices ? jc.w_slices.data() : nullptr;
+    jc.V3 = vol3(jc.job.g);
+    jc.Vp = tl::padded_sites(jc.V3);
+    jc.res_index.assign(jc.job.n_rhs, -1);
+    p->max_v3 = std::max(p->max_v3, jc.V3);
+    std::map<int, std::vector<int>> by_slot;
+    for (int r = 0; r < jc.job.n_rhs; r++)
+      by_slot[slot_of(jc.job.g, jc.job.w_slices, jc.job.n_w_slices, jc.t_of_rhs[r])].push_back(r);
+    const size_t rb = align256((size_t)jc.Vp * tl::kVBytes[prec]);
+    for (auto& kv : by_slot) {
+      const int k = (int)kv.second.size();
+      const int ng = (k + max_width - 1) / max_width;
+      int done = 0;
+      for (int q = 0; q < ng; q++) {
+        const int nr = (k - done + (ng - q) - 1) / (ng - q);
+        tl_plan::Group gr{j, kv.first, (int)p->res.size(), nr};
+        for (int i = 0; i < nr; i++) {
+          const int r = kv.second[done + i];
+          jc.res_index[r] = (int)p->res.size();
+          p->res.push_back({j, r, kv.first, (int64_t)off});
+          off += rb;
+        }
+        done += nr;
+        p->width = std::max(p->width, nr);
+        p->groups.push_back(gr);
+      }
+    }
+    p->jobs.push_back(std::move(jc));
+  }
+  p->buf_bytes = std::max<size_t>(off, 256);
+
+  // device memory: two resident buffers and the tables
+  int rc = TL_OK;
+  for (int k = 0; k < 2 && rc == TL_OK; k++) {
+    void* b = nullptr;
+    rc = dev_alloc(c, &b, p->buf_bytes);
+    p->buf[k] = static_cast<char*>(b);
+  }
+  const size_t n_res = p->res.size();
+  const size_t gbytes = align256(p->groups.size() * sizeof(StepGroup));
+  const size_t obytes = align256(n_res * sizeof(int64_t));
+  const size_t rbytes = align256(n_res * sizeof(tl::RedField));
+  const size_t pbytes = align256((size_t)tl::red_partials_doubles((int)n_res, p->max_v3) * sizeof(double));
+  if (rc == TL_OK) {
+    void* t = nullptr;
+    rc = dev_alloc(c, &t, gbytes + obytes + rbytes + pbytes);
+    p->tables = static_cast<char*>(t);
+  }
+  if (rc == TL_OK) {
+    p->groups_dev = reinterpret_cast<StepGroup*>(p->tables);
+    p->packoff_dev = reinterpret_cast<int64_t*>(p->tables + gbytes);
+    p->red_dev = reinterpret_cast<tl::RedField*>(p->tables + gbytes + obytes);
+    p->partials = reinterpret_cast<double*>(p->tables + gbytes + obytes + rbytes);
+    std::vector<int64_t> po;
+    std::vector<tl::RedField> rf;
+    for (auto& jc : p->jobs) {
+      p->packoff_first.push_back((int64_t)po.size());
+      for (int r = 0; r < jc.job.n_rhs; r++) po.push_back(p->res[jc.res_index[r]].off);
+    }
+    for (auto& jc : p->jobs)
+      for (int r = 0; r < jc.job.n_rhs; r++) {
+        const int64_t o = p->res[jc.res_index[r]].off;
+        rf.push_back({o, o, jc.V3, jc.Vp, 0});
+      }
+    int64_t oo = 0;
+    for (auto& f : rf) {
+      f.out_off = oo;
+      oo += f.V3;
+    }
+    rc = upload(c, p->packoff_dev, po.data(), po.size() * sizeof(int64_t));
+    if (rc == TL_OK) rc = upload(c, p->red_dev, rf.data(), rf.size() * sizeof(tl::RedField));
+  }
+  if (rc == TL_OK) {
+    // zero the resident buffers so tuning runs never see stale bit patterns
+    for (int k = 0; k < 2 && rc == TL_OK; k++)
+      if (hipMemsetAsync(p->buf[k], 0, p->buf_bytes, c->stream) != hipSuccess)
+        rc = fail(c, TL_ERR_HIP, "hipMemsetAsync failed");
+  }
+  if (rc == TL_OK) rc = plan_upload_groups(p, p->cfg);
+  if (rc != TL_OK) {
+    plan_free(p);
+    return rc;
+  }
+  // info
+  tl_plan_info& in = p->info;
+  in.n_groups = (int32_t)p->groups.size();
+  in.group_width = p->width;
+  in.launches_per_step = (flags & TL_PLAIN) ? in.n_groups : 1;
+  double bytes = 0.0;
+  int64_t rs = 0;
+  for (auto& gr : p->groups) {
+    const double v3 = (double)p->jobs[gr.job].V3;
+    bytes += v3 * (3.0 * tl::kWBytes[prec] + 2.0 * gr.nr * tl::kVBytes[prec]);
+    rs += (int64_t)p->jobs[gr.job].V3 * gr.nr;
+  }
+  in.rhs_sites = rs;
+  in.bytes_per_step = bytes;
+  in.flops_per_step = 444.0 * (double)rs;
+  in.resident_bytes = (int64_t)(2 * p->buf_bytes + gbytes + obytes + rbytes + pbytes);
+  *out = p;
+  return TL_OK;
+}
+
+int tl_plan_load(tl_plan* p) {
+  if (!p) return TL_ERR_ARG;
+  tl_ctx* c = p->ctx;
+  DeviceGuard dg(c->device);
+  for (size_t j = 0; j < p->jobs.size(); j++) {
+    const auto& jc = p->jobs[j];
+    TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(p->prec, jc.job.psi, p->buf[p->cur], p->packoff_dev + p->packoff_first[j],
+                                        jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+  }
+  return TL_OK;
+}
+
+int tl_plan_run(tl_plan* p) {
+  if (!p) return TL_ERR_ARG;
+  tl_ctx* c = p->ctx;
+  if (p->n_steps == 0) return TL_OK;
+  DeviceGuard dg(c->device);
+  TL_TRY(plan_prepare(p));
+  if (p->flags & TL_GRAPH) {
+    TL_TRY(plan_capture(p, p->cur));
+    if (c->fault_launch) return fail(c, TL_ERR_HIP, "graph launch failed (TL_FAULT=launch)");
+    HIP_TRY(c, hipGraphLaunch(p->graph[p->cur], c->stream));
+  } else {
+    TL_TRY(plan_enqueue(p, c->stream, p->cur));
+  }
+  p->cur ^= (p->n_steps & 1);
+  return TL_OK;
+}
+
+int tl_plan_store(tl_plan* p) {
+  if (!p) return TL_ERR_ARG;
+  tl_ctx* c = p->ctx;
+  DeviceGuard dg(c->device);
+  for (size_t j = 0; j < p->jobs.size(); j++) {
+    const auto& jc = p->jobs[j];
+    TL_TRY(launch(c, "unpack", [&] { return tl::launch_unpack(p->prec, p->buf[p->cur], jc.job.psi, p->packoff_dev + p->packoff_first[j],
+                                          jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+  }
+  return TL_OK;
+}
+
+int tl_plan_reduce(tl_plan* p, int kind, const tl_plan* other, double* out) {
+  if (!p) return TL_ERR_ARG;
+  tl_ctx* c = p->ctx;
+  if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
+  if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
+  const char* b = nullptr;
+  if (kind == TL_DOT) {
+    if (!other) return fail(c, TL_ERR_ARG, "TL_DOT needs a second plan");
+    if (other->ctx != c || other->prec != p->prec || other->buf_bytes != p->buf_bytes || other->res.size() != p->res.size())
+      return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in context, precision or shape");
+    for (size_t i = 0; i < p->res.size(); i++)
+      if (other->res[i].off != p->res[i].off) return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in layout");
+    b = other->buf[other->cur];
+  }
+  DeviceGuard dg(c->device);
+  // a (this) is the second argument of <other, this>
+  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, p->prec, p->buf[p->cur], b, p->red_dev, (int)p->res.size(), p->max_v3,
+                                        p->partials, out, c->stream); });
+}
+
+int tl_plan_time(tl_plan* p, int reps, double* ms_per_step) {
+  if (!p) return TL_ERR_ARG;
+  tl_ctx* c = p->ctx;
+  if (reps < 1 || !ms_per_step) return fail(c, TL_ERR_ARG, "need reps >= 1 and an output pointer");
+  if (p->n_steps == 0) return fail(c, TL_ERR_ARG, "plan has no steps");
+  DeviceGuard dg(c->device);
+  TL_TRY(tl_plan_run(p));   // tuning and graph capture happen outside the timed region
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  int rc = TL_OK;
+  (void)hipEventRecord(e0, c->stream);
+  for (int k = 0; k < reps && rc == TL_OK; k++) rc = tl_plan_run(p);
+  (void)hipEventRecord(e1, c->stream);
+  float ms = 0.0f;
+  if (rc == TL_OK) {
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = fail(c, TL_ERR_HIP, "event timing failed");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == TL_OK) *ms_per_step = ms / ((double)reps * p->n_steps * p->info.launches_per_step);
+  return rc;
+}
+
+int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
+  if (!p || !info) return TL_ERR_ARG;
+  *info = p->info;
+  info->n_tiles = p->n_tiles;
+  info->variant = p->cfg.variant;
+  info->block = p->cfg.block;
+  info->tz = p->cfg.tz;
+  info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
+  return TL_OK;
+}
+
+int tl_plan_destroy(tl_plan* p) {
+  if (!p) return TL_ERR_ARG;
+  plan_free(p);
+  return TL_OK;
+}
+
+int tl_smear(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags) {
+  if (!c) return TL_ERR_ARG;
+  tl_plan* p = nullptr;
+  TL_TRY(tl_plan_create(c, jobs, n_jobs, n_steps, sigma, prec, flags, &p));
+  int rc = tl_plan_load(p);
+  if (rc == TL_OK) rc = tl_plan_run(p);
+  if (rc == TL_OK) rc = tl_plan_store(p);
+  plan_free(p);   // waits for the queued work before releasing the resident buffers
+  return rc;
+}
+
+int tl_reduce(tl_ctx* c, int kind, int64_t n_sites, int n_rhs, const void* psi, const void* phi, double* out) {
+  if (!c) return TL_ERR_ARG;
+  if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
+  if (n_sites < 1 || n_rhs < 1) return fail(c, TL_ERR_ARG, "need n_sites >= 1 and n_rhs >= 1");
+  if (!psi || !out || (kind == TL_DOT && !phi)) return fail(c, TL_ERR_ARG, "NULL field or output");
+  if (n_sites > (int64_t(1) << 40)) return fail(c, TL_ERR_SHAPE, "n_sites too large");
+  TL_TRY(need_device(c));
+  DeviceGuard dg(c->device);
+  std::vector<tl::RedField> rf(n_rhs);
+  for (int r = 0; r < n_rhs; r++) rf[r] = {(int64_t)r * n_sites * 3, (int64_t)r * n_sites * 3, n_sites, 0, (int64_t)r * n_sites};
+  const size_t fbytes = align256(rf.size() * sizeof(tl::RedField));
+  const size_t pbytes = (size_t)tl::red_partials_doubles(n_rhs, n_sites) * sizeof(double);
+  char* s = nullptr;
+  TL_TRY(ctx_scratch(c, fbytes + pbytes, &s));
+  TL_TRY(upload(c, s, rf.data(), rf.size() * sizeof(tl::RedField)));
+  // a = psi, b = phi: <phi, psi>
+  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, -1, static_cast<const char*>(psi), static_cast<const char*>(phi),
+                                        reinterpret_cast<const tl::RedField*>(s), n_rhs, n_sites,
+                                        reinterpret_cast<double*>(s + fbytes), out, c->stream); });
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""Test-side numpy readers of the packed storage formats of libtwolink.
+
+Written from the format description (planes of fixed-width words per site,
+reals in (re, im) order; F16S = half times an FP32 per-site scale), not from
+the library's code, so that the GPU's stored two-link field can be compared
+with the oracle's product element by element, and the colour-vector storage
+rounding can be checked bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+W_BYTES = {"f64": 144, "f32": 72, "f16s": 40, "bf16": 36}
+V_BYTES = {"f64": 48, "f32": 24, "f16s": 16, "bf16": 12}
+
+
+def padded(v3: int) -> int:
+    return (v3 + 63) // 64 * 64
+
+
+def _bf16_to_f32(u16: np.ndarray) -> np.ndarray:
+    return (u16.astype(np.uint32) << 16).view(np.float32)
+
+
+def decode_twolinks(raw: np.ndarray, L, prec: str, n_slots: int) -> np.ndarray:
+    """Packed two-link bytes -> complex128 [slot][Lz][Ly][Lx][mu][3][3]."""
+    Lx, Ly, Lz = L[:3]
+    v3 = Lx * Ly * Lz
+    vp = padded(v3)
+    wb = W_BYTES[prec]
+    raw = np.ascontiguousarray(raw[: n_slots * 3 * vp * wb]).reshape(n_slots, 3, vp * wb)
+    reals = np.empty((n_slots, 3, v3, 18), np.float64)
+    for s in range(n_slots):
+        for mu in range(3):
+            blk = raw[s, mu]
+            if prec == "f64":
+                planes = blk.view(np.float64).reshape(9, vp, 2)[:, :v3, :]
+                reals[s, mu] = planes.transpose(1, 0, 2).reshape(v3, 18)
+            elif prec == "f32":
+                p4 = blk[: 64 * vp].view(np.float32).reshape(4, vp, 4)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 16)
+                p2 = blk[64 * vp: 72 * vp].view(np.float32).reshape(vp, 2)[:v3]
+                reals[s, mu] = np.concatenate([p4, p2], axis=1)
+            elif prec == "bf16":
+                p8 = blk[: 32 * vp].view(np.uint16).reshape(2, vp, 8)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 16)
+                p2 = blk[32 * vp: 36 * vp].view(np.uint16).reshape(vp, 2)[:v3]
+                reals[s, mu] = _bf16_to_f32(np.concatenate([p8, p2], axis=1))
+            elif prec == "f16s":
+                p8 = blk[: 32 * vp].view(np.float16).reshape(2, vp, 8)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 16)
+                tail = blk[32 * vp: 40 * vp].reshape(vp, 8)[:v3]
+                h2 = tail[:, :4].copy().view(np.float16).reshape(v3, 2)
+                scale = tail[:, 4:].copy().view(np.float32).reshape(v3, 1)
+                reals[s, mu] = np.concatenate([p8, h2], axis=1).astype(np.float32) * scale
+            else:
+                raise ValueError(prec)
+    c = reals[..., 0::2] + 1j * reals[..., 1::2]          # [slot][mu][v3][9]
+    c = c.transpose(0, 2, 1, 3).reshape(n_slots, Lz, Ly, Lx, 3, 3, 3)
+    return c
+
+
+def f32_to_bf16_rne(x: np.ndarray) -> np.ndarray:
+    """float32 -> bf16 bits with round-to-nearest-even (finite inputs)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def storage_round_vectors(psi: np.ndarray, prec: str) -> np.ndarray:
+    """What storing complex128 colour vectors [..][3] in `prec` and reading them back gives."""
+    re = np.stack([psi.real, psi.imag], axis=-1).reshape(psi.shape[:-1] + (6,))
+    if prec == "f64":
+        out = re
+    elif prec == "f32":
+        out = re.astype(np.float32).astype(np.float64)
+    elif prec == "bf16":
+        out = _bf16_to_f32(f32_to_bf16_rne(re.astype(np.float32))).astype(np.float64)
+    elif prec == "f16s":
+        f = re.astype(np.float32)
+        mx = np.max(np.abs(f), axis=-1, keepdims=True)
+        with np.errstate(divide="ignore"):
+            inv = np.where(mx > 0, np.float32(1.0) / np.where(mx > 0, mx, np.float32(1)), np.float32(0))
+        h = (f * inv.astype(np.float32)).astype(np.float16)
+        out = (h.astype(np.float32) * mx).astype(np.float64)
+    else:
+        raise ValueError(prec)
+    out = out.reshape(psi.shape[:-1] + (3, 2))
+    return out[..., 0] + 1j * out[..., 1]

@@ -1,0 +1,310 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle, at
+sizes the oracle finishes in seconds: ragged tiles, odd extents, L = 1, 2, 4,
+every precision, every launch mode."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import checks
+from paper_2301_05518_amd import synth
+from tests import helpers as H
+from tests import packed
+from tests.gpu_common import errors, gpu_smear, log, to_dev, tol
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["f64", "f32", "f16s", "bf16"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2301_05518_amd as tl
+    c = tl.Context(0)
+    yield c
+    c.close()
+
+
+def rng(k):
+    return np.random.default_rng([4242, k])
+
+
+def haar(L, seed):
+    return synth.gauge_field(L, "haar", seed)
+
+
+# ------------------------------------------------------------------ build
+
+BUILD_SHAPES = [(6, 5, 7, 3), (4, 4, 4, 2), (17, 9, 5, 2), (1, 2, 3, 2), (64, 3, 2, 1)]
+
+
+@pytest.mark.parametrize("L", BUILD_SHAPES, ids=[str(s) for s in BUILD_SHAPES])
+def test_build_fp64_equals_product(ctx, orc, torch, L):
+    log(f"build f64 {L}")
+    U = haar(L, 1 + L[0])
+    W = ctx.build_twolinks(L, to_dev(U), "f64")
+    torch.cuda.synchronize()
+    got = packed.decode_twolinks(W.cpu().numpy(), L, "f64", L[3])
+    ref = orc.build_twolinks(U)
+    assert np.abs(got - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "bf16"])
+def test_build_storage_rounding(ctx, orc, torch, prec):
+    L = (10, 6, 7, 2)
+    log(f"build {prec} {L}")
+    U = haar(L, 7)
+    W = ctx.build_twolinks(L, to_dev(U), prec)
+    torch.cuda.synchronize()
+    got = packed.decode_twolinks(W.cpu().numpy(), L, prec, L[3])
+    ref = orc.build_twolinks(U)
+    # one rounding of entries of modulus <= 1 (SU(3)): half an ulp at 1 plus FP32 double-rounding slack
+    bound = {"f32": 2.0 ** -24, "f16s": 2.0 ** -11 * 1.01, "bf16": 2.0 ** -8 * 1.01}[prec]
+    d = np.maximum(np.abs(got.real - ref.real), np.abs(got.imag - ref.imag)).max()
+    assert d <= bound, d
+
+
+def test_build_slice_subset(ctx, orc, torch):
+    L = (6, 4, 5, 4)
+    U = haar(L, 3)
+    W = ctx.build_twolinks(L, to_dev(U), "f64", slices=[2, 0, 3])
+    torch.cuda.synchronize()
+    got = packed.decode_twolinks(W.cpu().numpy(), L, "f64", 3)
+    ref = orc.build_twolinks(U)
+    for slot, t in enumerate([2, 0, 3]):
+        assert np.abs(got[slot] - ref[t]).max() < 1e-14
+
+
+# ------------------------------------------------------------------ Laplacian
+
+LAP_SHAPES = [(4, 4, 4, 1), (2, 3, 5, 2), (1, 1, 1, 1), (1, 6, 2, 1), (17, 9, 5, 2), (8, 8, 8, 3), (33, 2, 4, 1)]
+
+
+@pytest.mark.parametrize("L", LAP_SHAPES, ids=[str(s) for s in LAP_SHAPES])
+def test_laplacian_fp64(ctx, orc, torch, L):
+    log(f"laplacian f64 {L}")
+    U = haar(L, 11)
+    Ud = to_dev(U)
+    W = ctx.build_twolinks(L, Ud, "f64")
+    Wo = orc.build_twolinks(U)
+    for t in range(L[3]):
+        psi = synth.random_field(rng(t), (L[2], L[1], L[0], 3))
+        out = ctx.laplacian(L, W, "f64", t, to_dev(psi))
+        torch.cuda.synchronize()
+        ref = orc.laplacian(Wo, t, psi)
+        assert checks.max_rel(out.cpu().numpy(), ref) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "bf16"])
+def test_laplacian_mixed(ctx, orc, torch, prec):
+    L = (12, 10, 9, 2)
+    U = haar(L, 12)
+    W = ctx.build_twolinks(L, to_dev(U), prec)
+    psi = synth.random_field(rng(5), (L[2], L[1], L[0], 3))
+    out = ctx.laplacian(L, W, prec, 1, to_dev(psi)).cpu().numpy()
+    ref = orc.laplacian(orc.build_twolinks(U), 1, psi)
+    mr, l2 = errors(out, ref)
+    log(f"laplacian {prec}: max-rel {mr:.3e} l2-rel {l2:.3e}")
+    assert mr < tol(prec, 1) and l2 < tol(prec, 1)
+
+
+def test_laplacian_subset_slot(ctx, orc, torch):
+    L = (6, 6, 4, 5)
+    U = haar(L, 13)
+    W = ctx.build_twolinks(L, to_dev(U), "f64", slices=[4, 1])
+    psi = synth.random_field(rng(6), (4, 6, 6, 3))
+    out = ctx.laplacian(L, W, "f64", 1, to_dev(psi), w_slices=[4, 1]).cpu().numpy()
+    ref = orc.laplacian(orc.build_twolinks(U), 1, psi)
+    assert checks.max_rel(out, ref) < 1e-14
+
+
+# ------------------------------------------------------------------ smearing, FP64
+
+def test_smear_point_source_8cube(ctx, orc, torch):
+    """8^3x8, exp-of-anti-Hermitian links, point source, N=20, sigma=2 (the small workload)."""
+    wl = synth.workload(0)
+    lat = wl.lattices[0]
+    U = lat.links_array()
+    psi = lat.sources_array()
+    out = gpu_smear(ctx, [(lat.L, U, lat.t_of_rhs, psi)], wl.n_steps, wl.sigma, "f64")[0]
+    ref = orc.smear_batch(orc.build_twolinks(U), lat.t_of_rhs, wl.n_steps, wl.sigma, psi)
+    mr, l2 = errors(out, ref)
+    log(f"8^3x8 f64 N=20: max-rel {mr:.3e} l2-rel {l2:.3e}")
+    assert mr < 1e-12 and l2 < 1e-12
+
+
+MODES = {"batched": 0, "plain": 1, "graph": 2, "autotune": 4, "graph+autotune": 6}
+
+
+def test_smear_modes_bit_identical(ctx, orc, torch):
+    """Every launch mode gives the same bits; all match the oracle."""
+    import paper_2301_05518_amd as tl
+    L = (10, 6, 9, 4)
+    ts = [1, 3, 1, 1, 3, 0, 1]          # groups of 4, 2 and 1 RHS
+    U = haar(L, 21)
+    psi = synth.random_field(rng(21), (len(ts), L[2], L[1], L[0], 3))
+    ref = orc.smear_batch(orc.build_twolinks(U), ts, 9, 3.0, psi)
+    outs = {}
+    for name, flags in MODES.items():
+        outs[name] = gpu_smear(ctx, [(L, U, ts, psi)], 9, 3.0, "f64", flags)[0]
+        mr, l2 = errors(outs[name], ref)
+        log(f"mode {name}: max-rel {mr:.3e}")
+        assert mr < 1e-12 and l2 < 1e-12
+    for name in MODES:
+        assert np.array_equal(outs[name], outs["batched"]), name
+
+
+def test_smear_uneven_batch_fp64(ctx, orc, torch):
+    shapes = [((6, 4, 8, 3), [0, 2]), ((9, 7, 5, 2), [1, 1, 1]), ((4, 4, 4, 1), [0])]
+    lats, refs = [], []
+    for k, (L, ts) in enumerate(shapes):
+        U = haar(L, 30 + k)
+        psi = synth.random_field(rng(30 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+        refs.append(orc.smear_batch(orc.build_twolinks(U), ts, 12, 4.0, psi))
+    for flags in (0, 6):
+        outs = gpu_smear(ctx, lats, 12, 4.0, "f64", flags)
+        for o, r in zip(outs, refs):
+            assert checks.max_rel(o, r) < 1e-12
+
+
+def test_free_field_closed_form(ctx, torch):
+    """Unit links: the GPU result equals the exact free kernel (Fourier form), no C oracle involved."""
+    for L, n, sigma, x0 in (((8, 8, 8, 2), 20, 2.0, (0, 0, 0)), ((12, 6, 10, 1), 15, 3.0, (3, 1, 7))):
+        U = synth.unit_gauge(L)
+        psi = np.stack([synth.point_source(L[:3], c, x0) for c in range(3)])
+        out = gpu_smear(ctx, [(L, U, [L[3] - 1] * 3, psi)], n, sigma, "f64")[0]
+        k = checks.free_kernel_dft(L[:3], n, sigma, x0)
+        for c in range(3):
+            ref = np.zeros_like(out[c])
+            ref[..., c] = k
+            assert checks.max_rel(out[c], ref) < 1e-13
+
+
+def test_gauge_covariance(ctx, torch):
+    L = (8, 6, 6, 2)
+    U = haar(L, 40)
+    G = synth.gauge_transform(L, 41)
+    psi = synth.random_field(rng(40), (2, L[2], L[1], L[0], 3))
+    a = gpu_smear(ctx, [(L, H.transform_links(U, G), [0, 1], np.stack([H.transform_vector(psi[0], G[0]),
+                                                                          H.transform_vector(psi[1], G[1])]))],
+                  10, 4.0, "f64")[0]
+    b = gpu_smear(ctx, [(L, U, [0, 1], psi)], 10, 4.0, "f64")[0]
+    for r in range(2):
+        assert checks.max_rel(a[r], H.transform_vector(b[r], G[r])) < 1e-12
+
+
+def test_repeated_runs_and_parity(ctx, orc, torch):
+    """Two runs of an odd number of steps = one smearing with twice the steps (same sigma/n)."""
+    import paper_2301_05518_amd as tl
+    L = (6, 8, 6, 2)
+    U = haar(L, 50)
+    psi = synth.random_field(rng(50), (3, L[2], L[1], L[0], 3))
+    Wo = orc.build_twolinks(U)
+    for flags in (0, 2):
+        W = ctx.build_twolinks(L, to_dev(U), "f64")
+        p = to_dev(psi)
+        plan = ctx.plan([tl.Job(L, W, [1, 1, 0], p)], 5, 1.5, "f64", flags)
+        plan.load()
+        plan.run()
+        plan.run()
+        plan.store()
+        torch.cuda.synchronize()
+        ref = orc.smear_batch(Wo, [1, 1, 0], 10, 3.0, psi)
+        assert checks.max_rel(p.cpu().numpy(), ref) < 1e-12
+        plan.close()
+
+
+# ------------------------------------------------------------------ mixed precision
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "bf16"])
+def test_smear_mixed_precision(ctx, orc, torch, prec):
+    L = (16, 16, 16, 2)
+    n, sigma = 40, 5.0
+    U = haar(L, 60)
+    psi = np.stack([synth.point_source(L[:3], c) for c in range(3)] + [synth.z2_source(rng(61), L[:3], 1)])
+    ts = [0, 0, 0, 1]
+    ref = orc.smear_batch(orc.build_twolinks(U), ts, n, sigma, psi)
+    out = gpu_smear(ctx, [(L, U, ts, psi)], n, sigma, prec, 6)[0]
+    mr, l2 = errors(out, ref)
+    log(f"16^3 {prec} N={n}: max-rel {mr:.3e} l2-rel {l2:.3e} (bar {tol(prec, n):.2e})")
+    assert mr < tol(prec, n) and l2 < tol(prec, n)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_steps_is_storage_roundtrip(ctx, torch, prec):
+    """n = 0: pack then unpack; equals storing in the precision, bit for bit."""
+    L = (7, 5, 3, 2)
+    U = haar(L, 70)
+    psi = synth.random_field(rng(70), (3, L[2], L[1], L[0], 3)) * np.array([1.0, 1e-3, 30.0])[:, None, None, None, None]
+    psi[1, 0, 0, 0] = 0.0          # an all-zero site (F16S scale 0)
+    out = gpu_smear(ctx, [(L, U, [0, 1, 0], psi)], 0, 0.0, prec)[0]
+    assert np.array_equal(out, packed.storage_round_vectors(psi, prec))
+
+
+# ------------------------------------------------------------------ reductions
+
+def test_reduce_natural(ctx, orc, torch):
+    psi = synth.random_field(rng(80), (3, 5, 6, 7, 3))
+    phi = synth.random_field(rng(81), (3, 5, 6, 7, 3))
+    n2 = ctx.reduce("norm2", to_dev(psi)).cpu().numpy()
+    dt = ctx.reduce("dot", to_dev(psi), to_dev(phi)).cpu().numpy()
+    sn = ctx.reduce("site_norm", to_dev(psi)).cpu().numpy()
+    for r in range(3):
+        assert abs(n2[r] - orc.norm2(psi[r])) < 1e-13 * n2[r]
+        d = orc.dot(phi[r], psi[r])
+        assert abs(dt[r] - d) < 1e-13 * abs(d)
+        assert np.abs(sn[r] - orc.site_norms(psi[r])).max() < 1e-14 * sn[r].max()
+    again = ctx.reduce("norm2", to_dev(psi)).cpu().numpy()
+    assert np.array_equal(n2, again)        # fixed summation order
+
+
+def test_plan_reductions(ctx, orc, torch):
+    import paper_2301_05518_amd as tl
+    L = (8, 6, 10, 2)
+    U = haar(L, 90)
+    psi = synth.random_field(rng(90), (3, L[2], L[1], L[0], 3))
+    Wo = orc.build_twolinks(U)
+    ref = orc.smear_batch(Wo, [1, 0, 1], 8, 2.0, psi)
+    W = ctx.build_twolinks(L, to_dev(U), "f64")
+    a = ctx.plan([tl.Job(L, W, [1, 0, 1], to_dev(psi))], 8, 2.0, "f64", 0)
+    b = ctx.plan([tl.Job(L, W, [1, 0, 1], to_dev(psi))], 8, 2.0, "f64", 0)
+    a.load(); a.run()
+    b.load()
+    n2 = a.reduce("norm2").cpu().numpy()
+    sn = a.reduce("site_norm").cpu().numpy().reshape(3, L[2], L[1], L[0])
+    dt = a.reduce("dot", b).cpu().numpy()        # <psi_initial, psi_smeared>
+    for r in range(3):
+        assert abs(n2[r] - orc.norm2(ref[r])) < 1e-12 * n2[r]
+        assert np.abs(sn[r] - orc.site_norms(ref[r])).max() < 1e-12 * sn[r].max()
+        d = orc.dot(psi[r], ref[r])
+        assert abs(dt[r] - d) < 1e-12 * abs(d)
+    a.close(); b.close()
+
+
+# ------------------------------------------------------------------ error paths (host-forced)
+
+@pytest.mark.parametrize("mode", ["alloc", "launch"])
+def test_fault_hooks(torch, mode, monkeypatch):
+    """TL_FAULT makes the library take its error paths without running a kernel."""
+    import paper_2301_05518_amd as tl
+    monkeypatch.setenv("TL_FAULT", mode)
+    c = tl.Context(0)
+    L = (4, 4, 4, 1)
+    U = to_dev(synth.unit_gauge(L))
+    W = torch.zeros(tl.twolinks_bytes(L, "f64"), dtype=torch.uint8, device="cuda")
+    p = to_dev(synth.point_source(L[:3], 0)[None])
+    if mode == "launch":
+        with pytest.raises(tl.TwolinkError, match="TL_ERR_HIP"):
+            c.build_twolinks(L, U, "f64", W=W)
+    with pytest.raises(tl.TwolinkError, match="TL_ERR_NOMEM" if mode == "alloc" else "TL_ERR_HIP"):
+        c.smear([tl.Job(L, W, [0], p)], 4, 1.0, "f64")
+    c.close()
