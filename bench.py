@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-link smearing path on one MI355X.
+
+One timed step is one pass of the whole path over a batch of synthetic
+input already resident in HBM: two-link build (FP64 product, stored in the
+batch precision, for the slices the sources live on), packing of the
+complex128 sources into the resident storage format, n smearing steps (one
+persistent fused launch per step, all right-hand sides together, replayed
+from a HIP graph), FP64 norms of every smeared field, and unpacking back to
+complex128.  The plan (resident buffers, work list, tuned tiling, captured
+graph) is created once before timing and reused by every pass.
+
+Default workload: 64^3x96 lattice, Haar SU(3) links, 3 colour wall sources
+on each of 8 time slices (24 RHS), n = 60, sigma = 6, FP32 storage and
+arithmetic.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload 3] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+METRIC = "smeared site-updates/s per RHS + % HBM roofline; FP64 vs batched mixed precision"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--cpu-rhs", type=int, default=12, help="RHS in the CPU oracle sample")
+    ap.add_argument("--flags", type=int, default=6, help="plan flags (2 graph | 4 autotune)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("tl_kernels.hip", "tl_format.h", "tl_internal.h"):
+        with open(os.path.join(ROOT, "paper_2301_05518_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per step-kernel launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload_key)
+    except (ValueError, OSError):
+        return None
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def links_on_device(torch, lat, dev, workers):
+    """Gauge field [Lt][Lz][Ly][Lx][4][3][3] on the GPU, drawn slice by slice on the host."""
+    from paper_2301_05518_amd import synth
+    Lx, Ly, Lz, Lt = lat.L
+    U = torch.empty((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=torch.complex128, device=dev)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = [ex.submit(synth.gauge_slice, lat.L, lat.links, lat.link_seed, t) for t in range(Lt)]
+        for t, f in enumerate(futs):
+            U[t].copy_(torch.from_numpy(f.result()))
+    return U
+
+
+def cpu_baseline(lat, wl, U_dev, n_rhs_sample):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import core
+    orc = core.get()
+    ts = lat.t_of_rhs[:n_rhs_sample]
+    slices = sorted(set(ts))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    updates = 0
+    for t in slices:
+        u = U_dev[t:t + 1].cpu().numpy()
+        Wt = orc.build_twolinks(u)
+        for r, tr in enumerate(ts):
+            if tr != t:
+                continue
+            orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
+            updates += lat.V3 * wl.n_steps
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "RHS-site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ts)} of {len(lat.t_of_rhs)} RHS ({len(slices)} slices, {lat.L[0]}^3) x {wl.n_steps} "
+                      f"steps incl. their two-link builds, FP64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the path shards by time slice with no "
+                                   "exchange, but multi-GPU runs are not implemented; use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2301_05518_amd as tl
+    from paper_2301_05518_amd import synth
+
+    dev = torch.device("cuda", 0)
+    wl = synth.workload(args.workload)
+    prec = wl.precisions[0]
+    workers = min(16, os.cpu_count() or 1)
+    log(f"[bench] workload {args.workload}: {wl.name}; drawing inputs")
+    t_in = time.perf_counter()
+    jobs_in = []
+    for lat in wl.lattices:
+        U = links_on_device(torch, lat, dev, workers)
+        psi = torch.from_numpy(lat.sources_array()).to(dev)
+        slices = sorted(set(lat.t_of_rhs))
+        jobs_in.append((lat, U, psi, slices))
+    torch.cuda.synchronize()
+    log(f"[bench] inputs resident in HBM ({time.perf_counter() - t_in:.1f} s)")
+
+    ctx = tl.Context(0)
+    jobs = []
+    for lat, U, psi, slices in jobs_in:
+        W = ctx.build_twolinks(lat.L, U, prec, slices=slices)
+        jobs.append(tl.Job(lat.L, W, lat.t_of_rhs, psi, slices))
+    plan = ctx.plan(jobs, wl.n_steps, wl.sigma, prec, args.flags)
+    n_rhs = sum(len(l.t_of_rhs) for l in wl.lattices)
+
+    def one_pass():
+        for (lat, U, _, slices), j in zip(jobs_in, jobs):
+            ctx.build_twolinks(lat.L, U, prec, slices=slices, W=j.W)
+        plan.load()
+        plan.run()
+        norms = plan.reduce("norm2")
+        plan.store()
+        return norms
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    log("[bench] warm; timing")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        norms = one_pass()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    updates = wl.rhs_site_updates
+    value = updates / (ms_per_step * 1e-3)
+    finite = bool(torch.isfinite(norms).all().item())
+    log(f"[bench] pass {ms_per_step:.3f} ms -> {value:.4e} RHS-site-updates/s")
+
+    # dominant kernel: the smearing step, timed with HIP events on the library's stream
+    info = plan.info()
+    step_ms = plan.time(reps=3)
+    achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
+    key = f"workload{args.workload}"
+    traffic = measured_traffic(key)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "step_direct", "algorithmic_bytes_per_launch": info["bytes_per_step"],
+                "avg_launch_ms": round(step_ms, 5)}
+    log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
+
+    # the pieces of a pass, timed alone on the same stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=3):
+        fn()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    build_ms = timed(lambda: [ctx.build_twolinks(lat.L, U, prec, slices=s, W=j.W)
+                              for (lat, U, _, s), j in zip(jobs_in, jobs)])
+    pack_ms = timed(plan.load)
+    unpack_ms = timed(plan.store)
+    norm_ms = timed(lambda: plan.reduce("norm2"))
+    smear_ms = step_ms * wl.n_steps
+    lat0, U0 = jobs_in[0][0], jobs_in[0][1]
+    Wall = ctx.build_twolinks(lat0.L, U0, prec)
+    build_all_ms = timed(lambda: ctx.build_twolinks(lat0.L, U0, prec, W=Wall), reps=2)
+    del Wall
+    torch.cuda.empty_cache()
+    smear_rate = info["rhs_sites"] * wl.n_steps / (smear_ms * 1e-3)
+
+    # plain FP64: one RHS per launch, RHS in succession, eager launches
+    plain = None
+    if not args.no_plain:
+        pjobs = []
+        for (lat, U, psi, slices) in jobs_in:
+            W64 = ctx.build_twolinks(lat.L, U, "f64", slices=slices)
+            pjobs.append(tl.Job(lat.L, W64, lat.t_of_rhs, psi, slices))
+        p64 = ctx.plan(pjobs, wl.n_steps, wl.sigma, "f64", tl.TL_PLAIN)
+        p64.load()
+        launch_ms = p64.time(reps=1)
+        pinfo = p64.info()
+        plain_ms = launch_ms * pinfo["launches_per_step"] * wl.n_steps
+        plain_rate = pinfo["rhs_sites"] * wl.n_steps / (plain_ms * 1e-3)
+        plain = {"smear_ms": round(plain_ms, 3), "rate": plain_rate,
+                 "launch_us": round(launch_ms * 1e3, 2),
+                 "achieved_GBs": round(pinfo["bytes_per_step"] / (plain_ms / wl.n_steps * 1e-3) / 1e9, 1),
+                 "speedup_of_batched": round(smear_rate / plain_rate, 3)}
+        p64.close()
+        del pjobs
+        torch.cuda.empty_cache()
+        log(f"[bench] plain fp64 {plain_rate:.3e} /s; batched {prec} is {smear_rate / plain_rate:.2f}x")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle sample")
+        cpu = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], min(args.cpu_rhs, len(wl.lattices[0].t_of_rhs)))
+        log(f"[bench] oracle {cpu['value']:.3e} /s on {cpu['cores']} threads")
+
+    lat = wl.lattices[0]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "RHS-site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "lattices": [list(l.L) for l in wl.lattices],
+            "rhs": n_rhs,
+            "n_smear": wl.n_steps,
+            "sigma": wl.sigma,
+            "storage": prec,
+            "accumulate": "f64" if prec == "f64" else "f32",
+            "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
+            "tile": {k: info[k] for k in ("block", "tz", "grid", "n_tiles", "group_width")},
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "breakdown_ms": {"build": round(build_ms, 4), "pack": round(pack_ms, 4), "smear": round(smear_ms, 4),
+                         "norms": round(norm_ms, 4), "unpack": round(unpack_ms, 4),
+                         "build_all_slices": round(build_all_ms, 4)},
+        "smear_only_rate": smear_rate,
+        "plain_fp64": plain,
+        "finite": finite,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,94 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (graph + autotune, two-links built for the source slices).
+
+The oracle computes whole slices (one smeared output site depends on the
+whole slice after n >= L/4 steps), so each test compares every site of a
+sample of right-hand sides, each against an oracle run on that RHS's slice.
+"""
+import numpy as np
+import pytest
+
+from oracle import checks, core
+from paper_2301_05518_amd import synth
+from tests.gpu_common import errors, log, tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2301_05518_amd as tl
+    c = tl.Context(0)
+    yield c
+    c.close()
+
+
+def run_workload(ctx, torch, index, prec, flags, sample):
+    """Smear workload `index` on the GPU; compare `sample` RHS indices per lattice with the oracle."""
+    import paper_2301_05518_amd as tl
+    wl = synth.workload(index)
+    dev = torch.device("cuda", 0)
+    orc = core.get()
+    jobs, lats = [], []
+    for lat in wl.lattices:
+        Lx, Ly, Lz, Lt = lat.L
+        slices = sorted(set(lat.t_of_rhs))
+        # only the source slices' links are read when W is built for those slices
+        U = torch.zeros((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=torch.complex128, device=dev)
+        host = {}
+        for t in slices:
+            host[t] = synth.gauge_slice(lat.L, lat.links, lat.link_seed, t)
+            U[t].copy_(torch.from_numpy(host[t]))
+        W = ctx.build_twolinks(lat.L, U, prec, slices=slices)
+        psi = torch.from_numpy(lat.sources_array()).to(dev)
+        jobs.append(tl.Job(lat.L, W, lat.t_of_rhs, psi, slices))
+        lats.append((lat, host))
+        del U
+    log(f"workload {index} ({wl.name}) {prec}: smearing on the GPU")
+    ctx.smear(jobs, wl.n_steps, wl.sigma, prec, flags)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (lat, host), job in zip(lats, jobs):
+        for r in sample(len(lat.t_of_rhs)):
+            t = lat.t_of_rhs[r]
+            Wt = orc.build_twolinks(host[t][None])
+            ref = orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
+            got = job.psi[r].cpu().numpy()
+            mr, l2 = errors(got, ref)
+            log(f"  {lat.L} RHS {r} (t={t}): max-rel {mr:.3e} l2-rel {l2:.3e}")
+            worst = max(worst, mr, l2)
+    return worst, wl.n_steps
+
+
+def test_workload1_fp64_32cube(ctx, torch):
+    """32^3x64, 3 colour point sources, N=40, FP64: every RHS, batched and plain launches."""
+    for flags in (6, 1):
+        worst, n = run_workload(ctx, torch, 1, "f64", flags, lambda k: range(k))
+        assert worst < tol("f64", n)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_workload2_48cube(ctx, torch, prec):
+    """48^3x96, 3 colour point sources, N=40, FP32 and F16S: every RHS."""
+    worst, n = run_workload(ctx, torch, 2, prec, 6, lambda k: range(k))
+    assert worst < tol(prec, n)
+
+
+def test_workload3_64cube_24rhs(ctx, torch):
+    """64^3x96, 24 colour wall sources on 8 slices, N=60, FP32: 4 RHS sampled over slices and colours."""
+    worst, n = run_workload(ctx, torch, 3, "f32", 6, lambda k: [0, 7, 14, k - 1])
+    assert worst < tol("f32", n)
+
+
+def test_workload4_uneven_bf16(ctx, torch):
+    """Uneven batch 24^3x48 + 32^3x64 + 48^3x96, Z2 sources, N=40, BF16: first and last RHS of each lattice."""
+    worst, n = run_workload(ctx, torch, 4, "bf16", 6, lambda k: sorted({0, k - 1}))
+    assert worst < tol("bf16", n)
