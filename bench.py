@@ -45,8 +45,12 @@ def parse():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--cpu-rhs", type=int, default=12, help="RHS in the CPU oracle sample")
+    ap.add_argument("--cpu-rhs", type=int, default=24, help="RHS in the CPU oracle sample")
     ap.add_argument("--flags", type=int, default=6, help="plan flags (2 graph | 4 autotune)")
+    ap.add_argument("--tile", default=None, help="fixed step tiling 'variant,block,tz,grid' (no tuning)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
+                         "profiles/traffic.json and exit")
     return ap.parse_args()
 
 
@@ -71,6 +75,49 @@ def measured_traffic(workload_key: str):
     if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+COPY_BYTES = 1 << 30          # known-size device copy used to calibrate the byte counters
+
+
+def _counter_rows(d, counter):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") == counter:
+                    rows.append(row)
+    return rows
+
+
+def summarize_counters(fetch_dir, write_dir, workload_key, tile):
+    """Per-launch HBM bytes of the step kernel from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for a plain copy of COPY_BYTES."""
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        step = [float(r["Counter_Value"]) * 1024 for r in rows if "step_" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) * 1024 for r in rows
+                if "copyBuffer" in r["Kernel_Name"] or "copy_kernel" in r["Kernel_Name"]]
+        copy = [c for c in copy if c > 0.5 * COPY_BYTES]   # the calibration copy only
+        if not step or not copy:
+            raise SystemExit(f"no step-kernel or calibration-copy dispatches with {counter} in {d}")
+        scale = COPY_BYTES / (sum(copy) / len(copy))
+        out[counter] = {"raw_bytes_per_launch": sum(step) / len(step), "launches": len(step),
+                        "copy_raw_bytes": sum(copy) / len(copy), "scale": scale,
+                        "bytes_per_launch": sum(step) / len(step) * scale}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    allrec = json.load(open(path)) if os.path.exists(path) else {}
+    allrec[workload_key] = {
+        "kernel_source_hash": kernel_source_hash(), "tile": tile,
+        "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
+        "counters": out,
+    }
+    with open(path, "w") as fh:
+        json.dump(allrec, fh, indent=1)
+    print(json.dumps(allrec[workload_key], indent=1))
 
 
 def links_on_device(torch, lat, dev, workers):
@@ -111,6 +158,11 @@ def cpu_baseline(lat, wl, U_dev, n_rhs_sample):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, f"workload{args.workload}", args.tile)
+        return
+    if args.tile:
+        os.environ["TL_TILE"] = args.tile
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU: the path shards by time slice with no "
@@ -168,6 +220,21 @@ def main():
     finite = bool(torch.isfinite(norms).all().item())
     log(f"[bench] pass {ms_per_step:.3f} ms -> {value:.4e} RHS-site-updates/s")
 
+    # achievable streaming bandwidth: a plain device copy of a known size (also the
+    # calibration dispatch for the byte counters of a rocprofv3 --pmc run)
+    ca = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+    torch.cuda.empty_cache()
+
     # dominant kernel: the smearing step, timed with HIP events on the library's stream
     info = plan.info()
     step_ms = plan.time(reps=3)
@@ -176,8 +243,9 @@ def main():
     traffic = measured_traffic(key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "step_direct", "algorithmic_bytes_per_launch": info["bytes_per_step"],
-                "avg_launch_ms": round(step_ms, 5)}
+                "kernel": ["step_direct", "step_zmarch"][info["variant"]],
+                "algorithmic_bytes_per_launch": info["bytes_per_step"],
+                "avg_launch_ms": round(step_ms, 5), "copy_GBs": round(copy_gbs, 1)}
     log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 
     # the pieces of a pass, timed alone on the same stream
@@ -256,7 +324,7 @@ def main():
             "storage": prec,
             "accumulate": "f64" if prec == "f64" else "f32",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
-            "tile": {k: info[k] for k in ("block", "tz", "grid", "n_tiles", "group_width")},
+            "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "n_tiles", "group_width")},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

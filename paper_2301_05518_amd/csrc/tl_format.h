@@ -16,7 +16,9 @@
 // F16S stores value / s as IEEE half, with s = max |real| of the site (one
 // scale per site and direction for W, per site and RHS for vectors); s = 0
 // encodes an all-zero site.  Stores round to nearest even.  FP64 values
-// headed for half or bf16 are rounded to FP32 first.
+// headed for half or bf16 are rounded to FP32 first.  Vector quotients are
+// formed as v * RN(1/s) in FP32 (with v and s pre-multiplied by 2^64 when s is
+// subnormal); two-link quotients as v * (1/s) in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -175,9 +177,14 @@ template <> struct Fmt<F16S> {
       f[c] = (float)v[c];
       mx = fmaxf(mx, fabsf(f[c]));
     }
-    const float inv = mx > 0.0f ? 1.0f / mx : 0.0f;
-    reinterpret_cast<uint4*>(b)[i] = make_uint4(pack_h(f[0] * inv, f[1] * inv), pack_h(f[2] * inv, f[3] * inv),
-                                                pack_h(f[4] * inv, f[5] * inv), __float_as_uint(mx));
+    // q = v / s as half, computed as v * (1/s) in FP32.  A site whose maximum is
+    // an FP32 subnormal is first multiplied by 2^64 (exact), so 1/s cannot overflow.
+    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
+    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) f[c] = (f[c] * pre) * inv;
+    reinterpret_cast<uint4*>(b)[i] = make_uint4(pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]),
+                                                __float_as_uint(mx));
   }
 };
 

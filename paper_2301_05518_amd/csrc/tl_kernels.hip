@@ -178,6 +178,111 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
   }
 }
 
+// Variant 1: as variant 0, but each thread keeps the colour vectors of planes
+// z-2 .. z+2 in a register ring while it marches up the tile's z range, so the
+// z hops and the centre term read no memory; one new plane is loaded per step.
+template <int P, int R>
+__global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const char* pin = in + g.psi_off;
+    char* pout = out + g.psi_off;
+    const int nr = g.nr;
+    const int64_t rs = g.rhs_stride;
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    real ring[5][R][6];   // planes z-2, z-1, z, z+1, z+2
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(z0, k - 2, Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        if (r < nr) F::load_v(pin + r * rs, Vp, zo, ring[k][r]);
+    }
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t zp = (int64_t)wrap_step(z, 2, Lz) * LxLy + xy;
+      const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        if (r < nr) F::load_v(pin + r * rs, Vp, zp, ring[4][r]);
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, zo + xyp[mu], v);
+            mv_acc(m, v, acc[r]);
+          }
+        }
+        F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, zo + xym[mu], v);
+            mdv_acc(m, v, acc[r]);
+          }
+        }
+      }
+      {
+        real m[18];
+        F::load_w(Wmu[2], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mv_acc(m, ring[4][r], acc[r]);
+        F::load_w(Wmu[2], Vp, zm, m);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mdv_acc(m, ring[0][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        if (r < nr) {
+          real o[6];
+#pragma unroll
+          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+          F::store_v(pout + r * rs, Vp, site, o);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ build
 
 // W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in precision P.  One thread per site.
@@ -395,6 +500,14 @@ hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_g
   if (cfg.variant == 0) {
     step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
                                                  (real)alpha, (real)beta);
+  } else if (cfg.variant == 1) {
+    // FP64 with three or more RHS would spill the ring: the direct kernel computes the same bits
+    if (P == F64 && R > 2)
+      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                   (real)alpha, (real)beta);
+    else
+      step_zmarch<P, (P == F64 && R > 2) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
+                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
   } else {
     return hipErrorInvalidValue;
   }

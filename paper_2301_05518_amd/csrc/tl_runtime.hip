@@ -326,9 +326,13 @@ int plan_autotune(tl_plan* p) {
   }
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
-  for (int block : {256, 128, 64})
-    for (int tz : {1, 2, 4, 8, 16})
-      for (int occ : {0, 4, 8, 16}) cands.push_back({0, block, tz, occ ? occ * cu : 0});
+  for (int variant : {0, 1})
+    for (int block : {256, 128, 64})
+      for (int tz : {1, 2, 4, 8, 16}) {
+        if (variant == 1 && tz < 4) continue;   // the z ring pays off over several planes
+        if (variant == 1 && p->prec == TL_F64 && p->width > 2) continue;
+        for (int occ : {0, 4, 8, 16}) cands.push_back({variant, block, tz, occ ? occ * cu : 0});
+      }
   void* ref = nullptr;
   void* flag_mem = nullptr;
   TL_TRY(dev_alloc(c, &ref, p->buf_bytes));
@@ -374,8 +378,9 @@ int plan_autotune(tl_plan* p) {
       same = one == 0;
     }
     if (c->log)
-      fprintf(stderr, "[twolink] tune %s block=%d tz=%d grid=%d: %.4f ms/step%s\n", key.c_str(), p->cfg.block,
-              p->cfg.tz, p->cfg.grid, ms / reps, same ? "" : "  OUTPUT DIFFERS - rejected");
+      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d: %.4f ms/step%s\n", key.c_str(),
+              p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, ms / reps,
+              same ? "" : "  OUTPUT DIFFERS - rejected");
     if (same && ms < best) {
       best = ms;
       best_cfg = p->cfg;
@@ -392,9 +397,25 @@ int plan_autotune(tl_plan* p) {
   return plan_upload_groups(p, p->cfg);
 }
 
+// TL_TILE="variant,block,tz,grid" fixes the step configuration of every plan
+// (no tuning): used to profile or sweep one tiling at a time.
+bool tile_override(StepConfig* cfg) {
+  const char* e = getenv("TL_TILE");
+  if (!e) return false;
+  StepConfig c{};
+  if (sscanf(e, "%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid) != 4) return false;
+  if (c.variant < 0 || c.variant > 1 || c.block < 64 || c.block > 256 || c.block % 64 || c.tz < 1) return false;
+  *cfg = c;
+  return true;
+}
+
 int plan_prepare(tl_plan* p) {
   if (p->ready) return TL_OK;
-  if ((p->flags & TL_AUTOTUNE) && p->n_steps > 0) {
+  StepConfig forced{};
+  if (tile_override(&forced)) {
+    p->cfg = forced;
+    TL_TRY(plan_upload_groups(p, p->cfg));
+  } else if ((p->flags & TL_AUTOTUNE) && p->n_steps > 0) {
     TL_TRY(plan_autotune(p));
   }
   p->ready = true;

@@ -9,20 +9,27 @@ from oracle import checks
 
 # Tolerances (max-rel and L2-rel against the FP64 oracle).
 #   FP64: the target of the method, 1e-12.
-#   Mixed precision: n steps, each a contraction for sigma/n <= 2/3, each
-#   storing the vectors once with relative rounding error <= u after one
-#   rounding of the two-link field.  Worst case the errors add linearly,
-#   (n + 1) u; rounding errors of independent sites and steps add like a
-#   random walk, sqrt(n + 1) u.  The bar is 4 sqrt(n + 1) u with the storage
-#   unit roundoff u = 2^-24 (FP32), 2^-11 relative to the per-site maximum
-#   (F16S), 2^-8 (BF16); a wrong hop, sign or index gives O(1) errors.
+#   Mixed precision, n smearing steps: each step is a contraction for
+#   sigma/n <= 2/3 (|alpha| + 6 beta = 1 and |W| = 1), stores the vectors
+#   once (relative error <= u) and adds FP32 arithmetic and two-link
+#   rounding errors of about u more, so the error after n steps is at most
+#   about 2 (n + 1) u times the initial size.  Smooth fields (wall sources)
+#   accumulate their rounding errors coherently, so the linear bound is
+#   the right one.  u = 2^-24 (FP32), 2^-11 relative to the per-site
+#   maximum (F16S), 2^-8 (BF16).  Wrong hops, signs or indices give O(1)
+#   errors; the single-application Laplacian bound (16 u, allowing a
+#   four-fold cancellation between -6 psi and the hops) pins those tightly.
 UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16s": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
 def tol(prec: str, n: int) -> float:
     if prec == "f64":
         return 1e-12
-    return 4.0 * (n + 1) ** 0.5 * UNIT_ROUNDOFF[prec]
+    return 2.0 * (n + 1) * UNIT_ROUNDOFF[prec]
+
+
+def tol_lap(prec: str) -> float:
+    return 1e-14 if prec == "f64" else 16.0 * UNIT_ROUNDOFF[prec]
 
 
 def log(msg: str):

@@ -76,9 +76,10 @@ def storage_round_vectors(psi: np.ndarray, prec: str) -> np.ndarray:
     elif prec == "f16s":
         f = re.astype(np.float32)
         mx = np.max(np.abs(f), axis=-1, keepdims=True)
-        with np.errstate(divide="ignore"):
-            inv = np.where(mx > 0, np.float32(1.0) / np.where(mx > 0, mx, np.float32(1)), np.float32(0))
-        h = (f * inv.astype(np.float32)).astype(np.float16)
+        pre = np.where(mx < np.float32(2.0 ** -126), np.float32(2.0 ** 64), np.float32(1.0))
+        safe = np.where(mx > 0, mx * pre, np.float32(1.0))
+        inv = np.where(mx > 0, np.float32(1.0) / safe, np.float32(0.0)).astype(np.float32)
+        h = ((f * pre) * inv).astype(np.float16)
         out = (h.astype(np.float32) * mx).astype(np.float64)
     else:
         raise ValueError(prec)

@@ -64,7 +64,10 @@ def run_workload(ctx, torch, index, prec, flags, sample):
             got = job.psi[r].cpu().numpy()
             mr, l2 = errors(got, ref)
             log(f"  {lat.L} RHS {r} (t={t}): max-rel {mr:.3e} l2-rel {l2:.3e}")
-            worst = max(worst, mr, l2)
+            if not (np.isfinite(mr) and np.isfinite(l2)):
+                worst = float("inf")
+            else:
+                worst = max(worst, mr, l2)
     return worst, wl.n_steps
 
 
