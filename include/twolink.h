@@ -101,7 +101,7 @@ typedef struct {
     int32_t n_groups;          /* RHS groups: RHS of one slice that share each W load */
     int32_t group_width;       /* largest group */
     int32_t n_tiles;           /* work-list entries per step */
-    int32_t variant;           /* step kernel variant (0 direct, 1 z-marching) */
+    int32_t variant;           /* step kernel variant (0 direct, 1 z ring, 2 z ring + W_z ring) */
     int32_t block;             /* threads per workgroup */
     int32_t tz;                /* z planes per tile */
     int32_t grid;              /* workgroups per step launch */
@@ -116,6 +116,15 @@ typedef struct {
 
 /* Library version, major*10000 + minor*100 + patch. */
 int tl_version(void);
+
+/*
+ * Environment (read by the library):
+ *   TL_TILE="variant,block,tz,grid"  fix the step tiling of every plan (no tuning);
+ *                                    for profiling and sweeps
+ *   TL_LOG=1                         print autotuning candidates to stderr
+ *   TL_FAULT=alloc|launch            make internal allocations or launches fail
+ *                                    (read at tl_create; exercises error paths)
+ */
 
 /*
  * Create a context on HIP device `device`, queueing on `stream` (a

@@ -37,7 +37,9 @@ struct StepGroup {
 // Launch configuration of the step kernel.
 struct StepConfig {
   int variant;   // 0: one site per thread per z plane, neighbours through the caches
-                 // 1: z-marching with a register ring for the z hops
+                 // 1: z-marching with a register ring of colour vectors for the z hops
+                 // 2: z-marching with rings of colour vectors and z two-links, chunks
+                 //    marching in alternating directions
   int block;     // threads per workgroup (xy sites per tile)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile

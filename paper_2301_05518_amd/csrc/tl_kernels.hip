@@ -283,6 +283,144 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
   }
 }
 
+// Variant 2: z-marching with register rings for both the colour vectors of
+// planes z-2 .. z+2 and the z two-links of planes z-2 .. z, so every z hop
+// and the centre term read no memory and each W_z is loaded once.  Even
+// z chunks march up and odd chunks march down: two neighbouring chunks reach
+// the planes they share at the same time, so those halo planes are still in
+// L2 for the second reader.
+template <int P, int R>
+__global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ groups, int n_groups,
+                                                  int tile_base, int n_tiles, int tz,
+                                                  const char* __restrict__ in, char* __restrict__ out,
+                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const char* pin = in + g.psi_off;
+    char* pout = out + g.psi_off;
+    const int nr = g.nr;
+    const int64_t rs = g.rhs_stride;
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;       // first plane of the march
+    // ring[k] holds plane zs + dz*(k-2) relative to the current plane, i.e. k = 2 is
+    // the current plane and k = 4 the one two planes ahead in the march direction.
+    real ring[5][R][6];
+    // Each step loads one new W_z into wz[2]: W_z(z) marching up, W_z(z-2) marching
+    // down; wz[k] was loaded 2-k steps earlier.  So wz[k] = W_z(z-2+k) marching up
+    // and W_z(z-k) marching down: both hops' two-links are wz[0] and wz[2].
+    real wz[3][18];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        if (r < nr) F::load_v(pin + r * rs, Vp, zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
+      F::load_w(Wmu[2], Vp, zo, wz[k]);
+    }
+    for (int i = 0; i < nz; i++) {
+      const int z = zs + dz * i;
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      {
+        const int64_t za = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy + xy;   // two planes ahead
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) F::load_v(pin + r * rs, Vp, za, ring[4][r]);
+        // marching up the new W_z is the current plane's (forward hop); marching down it is the
+        // plane two below (backward hop)
+        const int64_t zw = up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+        F::load_w(Wmu[2], Vp, zw, wz[2]);
+      }
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, zo + xyp[mu], v);
+            mv_acc(m, v, acc[r]);
+          }
+        }
+        F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r < nr) {
+            real v[6];
+            F::load_v(pin + r * rs, Vp, zo + xym[mu], v);
+            mdv_acc(m, v, acc[r]);
+          }
+        }
+      }
+      // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mv_acc(wz[2], ring[4][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mdv_acc(wz[0], ring[0][r], acc[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mv_acc(wz[0], ring[0][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          if (r < nr) mdv_acc(wz[2], ring[4][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        if (r < nr) {
+          real o[6];
+#pragma unroll
+          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+          F::store_v(pout + r * rs, Vp, site, o);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ build
 
 // W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in precision P.  One thread per site.
@@ -508,6 +646,13 @@ hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_g
     else
       step_zmarch<P, (P == F64 && R > 2) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
                                                                              cfg.tz, in, out, (real)alpha, (real)beta);
+  } else if (cfg.variant == 2) {
+    if (P == F64 && R > 1)
+      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                   (real)alpha, (real)beta);
+    else
+      step_zring<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
+                                                                            cfg.tz, in, out, (real)alpha, (real)beta);
   } else {
     return hipErrorInvalidValue;
   }

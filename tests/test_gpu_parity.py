@@ -162,6 +162,33 @@ def test_smear_modes_bit_identical(ctx, orc, torch):
         assert np.array_equal(outs[name], outs["batched"]), name
 
 
+VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "1,128,5,512", "2,64,4,0", "2,128,3,0",
+                 "2,192,16,256", "2,64,1,8"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_variants_bit_identical(ctx, orc, torch, prec, monkeypatch):
+    """Every kernel variant and tiling (ragged xy tiles, ragged and alternating z chunks,
+    persistent grids) gives the same bits as the direct kernel."""
+    cases = [((10, 6, 13, 3), [0, 2, 0, 0]), ((5, 7, 2, 1), [0, 0]), ((8, 3, 1, 2), [1])]
+    lats = []
+    for k, (L, ts) in enumerate(cases):
+        U = haar(L, 25 + k)
+        psi = synth.random_field(rng(25 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+    outs = {}
+    for tile in VARIANT_TILES:
+        monkeypatch.setenv("TL_TILE", tile)
+        outs[tile] = gpu_smear(ctx, lats, 7, 2.5, prec)
+    for tile in VARIANT_TILES:
+        for a, b in zip(outs[tile], outs[VARIANT_TILES[0]]):
+            assert np.array_equal(a, b), tile
+    for (L, U, ts, psi), o in zip(lats, outs[VARIANT_TILES[0]]):
+        ref = orc.smear_batch(orc.build_twolinks(U), ts, 7, 2.5, psi)
+        mr, l2 = errors(o, ref)
+        assert mr < tol(prec, 7) and l2 < tol(prec, 7)
+
+
 def test_smear_uneven_batch_fp64(ctx, orc, torch):
     shapes = [((6, 4, 8, 3), [0, 2]), ((9, 7, 5, 2), [1, 1, 1]), ((4, 4, 4, 1), [0])]
     lats, refs = [], []
