@@ -101,7 +101,7 @@ typedef struct {
     int32_t n_groups;          /* RHS groups: RHS of one slice that share each W load */
     int32_t group_width;       /* largest group */
     int32_t n_tiles;           /* work-list entries per step */
-    int32_t variant;           /* step kernel variant (0 direct, 1 z ring, 2 z ring + W_z ring) */
+    int32_t variant;           /* step kernel variant (0 direct, 1-3 z-marching) */
     int32_t block;             /* threads per workgroup */
     int32_t tz;                /* z planes per tile */
     int32_t grid;              /* workgroups per step launch */

@@ -40,6 +40,8 @@ struct StepConfig {
                  // 1: z-marching with a register ring of colour vectors for the z hops
                  // 2: z-marching with rings of colour vectors and z two-links, chunks
                  //    marching in alternating directions
+                 // 3: as 2, with each plane's in-plane hops computed when the plane is
+                 //    first loaded (every plane read from memory once)
   int block;     // threads per workgroup (xy sites per tile)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile

@@ -124,10 +124,17 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
     const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};    // +2 in x, y
     const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};  // -2 in x, y
     const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
-    const char* pin = in + g.psi_off;
-    char* pout = out + g.psi_off;
     const int nr = g.nr;
-    const int64_t rs = g.rhs_stride;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, Lz);
     for (int z = z0; z < z1; z++) {
@@ -148,31 +155,25 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
         F::load_w(Wmu[mu], Vp, site, m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, fwd[mu], v);
-            mv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, fwd[mu], v);
+          mv_acc(m, v, acc[r]);
         }
         F::load_w(Wmu[mu], Vp, bwd[mu], m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, bwd[mu], v);
-            mdv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, bwd[mu], v);
+          mdv_acc(m, v, acc[r]);
         }
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        if (r < nr) {
-          real v[6], o[6];
-          F::load_v(pin + r * rs, Vp, site, v);
+        real v[6], o[6];
+        F::load_v(pin[r], Vp, site, v);
 #pragma unroll
-          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-          F::store_v(pout + r * rs, Vp, site, o);
-        }
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
+        if (r < nr) F::store_v(pout[r], Vp, site, o);
       }
     }
   }
@@ -204,10 +205,17 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
     const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
     const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
     const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
-    const char* pin = in + g.psi_off;
-    char* pout = out + g.psi_off;
     const int nr = g.nr;
-    const int64_t rs = g.rhs_stride;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, Lz);
     real ring[5][R][6];   // planes z-2, z-1, z, z+1, z+2
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
       const int64_t zo = (int64_t)wrap_step(z0, k - 2, Lz) * LxLy + xy;
 #pragma unroll
       for (int r = 0; r < R; r++)
-        if (r < nr) F::load_v(pin + r * rs, Vp, zo, ring[k][r]);
+        F::load_v(pin[r], Vp, zo, ring[k][r]);
     }
     for (int z = z0; z < z1; z++) {
       const int64_t zo = (int64_t)z * LxLy;
@@ -225,7 +233,7 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
       const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
 #pragma unroll
       for (int r = 0; r < R; r++)
-        if (r < nr) F::load_v(pin + r * rs, Vp, zp, ring[4][r]);
+        F::load_v(pin[r], Vp, zp, ring[4][r]);
       real acc[R][6];
 #pragma unroll
       for (int r = 0; r < R; r++)
@@ -237,20 +245,16 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
         F::load_w(Wmu[mu], Vp, site, m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, zo + xyp[mu], v);
-            mv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xyp[mu], v);
+          mv_acc(m, v, acc[r]);
         }
         F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, zo + xym[mu], v);
-            mdv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xym[mu], v);
+          mdv_acc(m, v, acc[r]);
         }
       }
       {
@@ -258,20 +262,18 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
         F::load_w(Wmu[2], Vp, site, m);
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mv_acc(m, ring[4][r], acc[r]);
+          mv_acc(m, ring[4][r], acc[r]);
         F::load_w(Wmu[2], Vp, zm, m);
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mdv_acc(m, ring[0][r], acc[r]);
+          mdv_acc(m, ring[0][r], acc[r]);
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        if (r < nr) {
-          real o[6];
+        real o[6];
 #pragma unroll
-          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-          F::store_v(pout + r * rs, Vp, site, o);
-        }
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::store_v(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -312,10 +314,17 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
     const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
     const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
     const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
-    const char* pin = in + g.psi_off;
-    char* pout = out + g.psi_off;
     const int nr = g.nr;
-    const int64_t rs = g.rhs_stride;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
     const int zlo = tzi * tz;
     const int nz = min(zlo + tz, Lz) - zlo;
     const bool up = (tzi & 1) == 0;
@@ -333,7 +342,7 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
       const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
 #pragma unroll
       for (int r = 0; r < R; r++)
-        if (r < nr) F::load_v(pin + r * rs, Vp, zo, ring[k][r]);
+        F::load_v(pin[r], Vp, zo, ring[k][r]);
     }
 #pragma unroll
     for (int k = 0; k < 2; k++) {
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
         const int64_t za = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy + xy;   // two planes ahead
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) F::load_v(pin + r * rs, Vp, za, ring[4][r]);
+          F::load_v(pin[r], Vp, za, ring[4][r]);
         // marching up the new W_z is the current plane's (forward hop); marching down it is the
         // plane two below (backward hop)
         const int64_t zw = up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
@@ -365,46 +374,40 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
         F::load_w(Wmu[mu], Vp, site, m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, zo + xyp[mu], v);
-            mv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xyp[mu], v);
+          mv_acc(m, v, acc[r]);
         }
         F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          if (r < nr) {
-            real v[6];
-            F::load_v(pin + r * rs, Vp, zo + xym[mu], v);
-            mdv_acc(m, v, acc[r]);
-          }
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xym[mu], v);
+          mdv_acc(m, v, acc[r]);
         }
       }
       // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
       if (up) {
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mv_acc(wz[2], ring[4][r], acc[r]);
+          mv_acc(wz[2], ring[4][r], acc[r]);
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mdv_acc(wz[0], ring[0][r], acc[r]);
+          mdv_acc(wz[0], ring[0][r], acc[r]);
       } else {
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mv_acc(wz[0], ring[0][r], acc[r]);
+          mv_acc(wz[0], ring[0][r], acc[r]);
 #pragma unroll
         for (int r = 0; r < R; r++)
-          if (r < nr) mdv_acc(wz[2], ring[4][r], acc[r]);
+          mdv_acc(wz[2], ring[4][r], acc[r]);
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        if (r < nr) {
-          real o[6];
+        real o[6];
 #pragma unroll
-          for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-          F::store_v(pout + r * rs, Vp, site, o);
-        }
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::store_v(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -417,6 +420,141 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
         wz[0][c] = wz[1][c];
         wz[1][c] = wz[2][c];
       }
+    }
+  }
+}
+
+// In-plane hops (x forward, x backward, y forward, y backward, in that order)
+// of the site xy of plane zo, for every RHS slot.
+template <class F, int R, typename real>
+__device__ __forceinline__ void inplane_hops(const char* const (&Wmu)[3], const char* const (&pin)[R], int64_t Vp,
+                                             int64_t zo, int xy, const int (&xyp)[2], const int (&xym)[2],
+                                             real (&acc)[R][6]) {
+#pragma unroll
+  for (int r = 0; r < R; r++)
+#pragma unroll
+    for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+  for (int mu = 0; mu < 2; mu++) {
+    real m[18];
+    F::load_w(Wmu[mu], Vp, zo + xy, m);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      real v[6];
+      F::load_v(pin[r], Vp, zo + xyp[mu], v);
+      mv_acc(m, v, acc[r]);
+    }
+    F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      real v[6];
+      F::load_v(pin[r], Vp, zo + xym[mu], v);
+      mdv_acc(m, v, acc[r]);
+    }
+  }
+}
+
+// Variant 3: z-marching in which every plane is read from memory once, at
+// the front of the march.  When plane f = z+2 is first touched, the thread
+// loads its own colour vectors there (register ring of planes z-2 .. z+2)
+// and also computes the in-plane hops of plane f, whose neighbour rows the
+// workgroup and its y-neighbour workgroups are loading in the same step, so
+// they come from L2.  Those partial sums wait in a ring for two steps; at
+// plane z the two z hops (W_z from a register ring) and the axpy complete
+// the site.  Chunks alternate their march direction as in variant 2.
+template <int P, int R>
+__global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* const Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;
+    real ring[5][R][6];      // own colour vectors, planes z-2dz .. z+2dz
+    real part[2][R][6];      // in-plane partial sums of planes z and z+dz
+    real wz[3][18];          // as in variant 2: wz[0], wz[2] are the two z hops' links
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int64_t zw = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
+      F::load_w(Wmu[2], Vp, zw, wz[k]);
+      const int64_t zp = (int64_t)wrap_step(zs, dz * k, Lz) * LxLy;
+      if (k < nz) inplane_hops<F, R>(Wmu, pin, Vp, zp, xy, xyp, xym, part[k]);
+    }
+    for (int i = 0; i < nz; i++) {
+      const int z = zs + dz * i;
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t zf = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy;   // front plane
+#pragma unroll
+      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zf + xy, ring[4][r]);
+      F::load_w(Wmu[2], Vp, up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy, wz[2]);
+      real front[R][6];
+      if (i + 2 < nz) inplane_hops<F, R>(Wmu, pin, Vp, zf, xy, xyp, xym, front);
+      // complete plane z: in-plane part, then z forward, then z backward, then the axpy
+      const real (&fw)[18] = up ? wz[2] : wz[0];
+      const real (&bw)[18] = up ? wz[0] : wz[2];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        mv_acc(fw, up ? ring[4][r] : ring[0][r], part[0][r]);
+        mdv_acc(bw, up ? ring[0][r] : ring[4][r], part[0][r]);
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, part[0][r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::store_v(pout[r], Vp, site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+          part[0][r][c] = part[1][r][c];
+          part[1][r][c] = front[r][c];
+        }
     }
   }
 }
@@ -653,6 +791,13 @@ hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_g
     else
       step_zring<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
+  } else if (cfg.variant == 3) {
+    if (P == F64 && R > 1)
+      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                   (real)alpha, (real)beta);
+    else
+      step_zfront<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
+                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
   } else {
     return hipErrorInvalidValue;
   }
