@@ -42,6 +42,7 @@ struct StepConfig {
                  //    marching in alternating directions
                  // 3: as 2, with each plane's in-plane hops computed when the plane is
                  //    first loaded (every plane read from memory once)
+                 // 4: as 0 with the direction loop rolled (fewer registers, more waves)
   int block;     // threads per workgroup (xy sites per tile)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile

@@ -559,6 +559,87 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
   }
 }
 
+// Variant 4: as variant 0, but the loop over directions stays rolled, so only
+// one direction's loads (two two-links and 2R colour vectors) are live at a
+// time.  Fewer registers allow more waves per SIMD, which hide the memory
+// latency of each direction and overlap one wave's arithmetic with the
+// others' loads.
+template <int P, int R>
+__global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xf = y * Lx + wrap_step(x, 2, Lx), xb = y * Lx + wrap_step(x, -2, Lx);
+    const int yf = wrap_step(y, 2, Ly) * Lx + x, yb = wrap_step(y, -2, Ly) * Lx + x;
+    const int nr = g.nr;
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t zf = (int64_t)wrap_step(z, 2, Lz) * LxLy + xy;
+      const int64_t zb = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+      const int64_t site = zo + xy;
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll 1
+      for (int mu = 0; mu < 3; mu++) {
+        const char* Wm = g.W + mu * g.w_mu_stride;
+        const int64_t f = mu == 0 ? zo + xf : (mu == 1 ? zo + yf : zf);
+        const int64_t b = mu == 0 ? zo + xb : (mu == 1 ? zo + yb : zb);
+        real m[18];
+        F::load_w(Wm, Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, f, v);
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wm, Vp, b, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, b, v);
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real v[6], o[6];
+        F::load_v(pin[r], Vp, site, v);
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
+        if (r < nr) F::store_v(pout[r], Vp, site, o);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ build
 
 // W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in precision P.  One thread per site.
@@ -791,6 +872,9 @@ hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_g
     else
       step_zring<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
+  } else if (cfg.variant == 4) {
+    step_rolled<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                 (real)alpha, (real)beta);
   } else if (cfg.variant == 3) {
     if (P == F64 && R > 1)
       step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,

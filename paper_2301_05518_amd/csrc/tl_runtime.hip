@@ -326,13 +326,13 @@ int plan_autotune(tl_plan* p) {
   }
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
-  for (int variant : {0, 1, 2, 3})
+  for (int variant : {0, 1, 2, 3, 4})
     for (int block : {256, 128, 64})
       for (int tz : {1, 2, 4, 8, 16, 32}) {
-        if (variant == 0 && tz > 16) continue;
-        if (variant >= 1 && tz < 4) continue;   // the z rings pay off over several planes
+        if ((variant == 0 || variant == 4) && tz > 16) continue;
+        if (variant >= 1 && variant <= 3 && tz < 4) continue;   // the z rings pay off over several planes
         if (variant == 1 && p->prec == TL_F64 && p->width > 2) continue;
-        if (variant >= 2 && p->prec == TL_F64 && p->width > 1) continue;
+        if ((variant == 2 || variant == 3) && p->prec == TL_F64 && p->width > 1) continue;
         for (int occ : {0, 4, 8, 16}) cands.push_back({variant, block, tz, occ ? occ * cu : 0});
       }
   void* ref = nullptr;
@@ -406,7 +406,7 @@ bool tile_override(StepConfig* cfg) {
   if (!e) return false;
   StepConfig c{};
   if (sscanf(e, "%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid) != 4) return false;
-  if (c.variant < 0 || c.variant > 3 || c.block < 64 || c.block > 256 || c.block % 64 || c.tz < 1) return false;
+  if (c.variant < 0 || c.variant > 4 || c.block < 64 || c.block > 256 || c.block % 64 || c.tz < 1) return false;
   *cfg = c;
   return true;
 }
