@@ -51,7 +51,19 @@ __device__ __forceinline__ uint32_t f32_to_h(float f) {
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) { return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16); }
 __device__ __forceinline__ uint32_t pack_h(float lo, float hi) { return f32_to_h(lo) | (f32_to_h(hi) << 16); }
 
-template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+// Store one word; NT = nontemporal (streamed past the caches: the smearing step's
+// output is not read again until the next step, long after it would be evicted).
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V* p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 template <int P> struct Fmt;
 
@@ -83,11 +95,11 @@ template <> struct Fmt<F64> {
       v[2 * c + 1] = (T)w.y;
     }
   }
-  template <typename T>
+  template <typename T, bool NT = false>
   __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
-    double2* p = reinterpret_cast<double2*>(b);
+    v2d* p = reinterpret_cast<v2d*>(b);
 #pragma unroll
-    for (int c = 0; c < 3; c++) p[c * Vp + i] = make_double2((double)v[2 * c], (double)v[2 * c + 1]);
+    for (int c = 0; c < 3; c++) put<NT>(p + c * Vp + i, v2d{(double)v[2 * c], (double)v[2 * c + 1]});
   }
 };
 
@@ -122,10 +134,10 @@ template <> struct Fmt<F32> {
     float2 c = reinterpret_cast<const float2*>(b + 16 * Vp)[i];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y;
   }
-  template <typename T>
+  template <typename T, bool NT = false>
   __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
-    reinterpret_cast<float4*>(b)[i] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-    reinterpret_cast<float2*>(b + 16 * Vp)[i] = make_float2((float)v[4], (float)v[5]);
+    put<NT>(reinterpret_cast<v4f*>(b) + i, v4f{(float)v[0], (float)v[1], (float)v[2], (float)v[3]});
+    put<NT>(reinterpret_cast<v2f*>(b + 16 * Vp) + i, v2f{(float)v[4], (float)v[5]});
   }
 };
 
@@ -167,7 +179,7 @@ template <> struct Fmt<F16S> {
     v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
     v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
   }
-  template <typename T>
+  template <typename T, bool NT = false>
   __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
     (void)Vp;
     float f[6];
@@ -183,8 +195,8 @@ template <> struct Fmt<F16S> {
     const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
 #pragma unroll
     for (int c = 0; c < 6; c++) f[c] = (f[c] * pre) * inv;
-    reinterpret_cast<uint4*>(b)[i] = make_uint4(pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]),
-                                                __float_as_uint(mx));
+    put<NT>(reinterpret_cast<v4u*>(b) + i,
+            v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
   }
 };
 
@@ -219,10 +231,10 @@ template <> struct Fmt<BF16> {
     v[2] = bf16_to_f32(p.y & 0xffffu); v[3] = bf16_to_f32(p.y >> 16);
     v[4] = bf16_to_f32(q & 0xffffu);   v[5] = bf16_to_f32(q >> 16);
   }
-  template <typename T>
+  template <typename T, bool NT = false>
   __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
-    reinterpret_cast<uint2*>(b)[i] = make_uint2(pack_bf16((float)v[0], (float)v[1]), pack_bf16((float)v[2], (float)v[3]));
-    reinterpret_cast<uint32_t*>(b + 8 * Vp)[i] = pack_bf16((float)v[4], (float)v[5]);
+    put<NT>(reinterpret_cast<v2u*>(b) + i, v2u{pack_bf16((float)v[0], (float)v[1]), pack_bf16((float)v[2], (float)v[3])});
+    put<NT>(reinterpret_cast<uint32_t*>(b + 8 * Vp) + i, pack_bf16((float)v[4], (float)v[5]));
   }
 };
 

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
         F::load_v(pin[r], Vp, site, v);
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-        if (r < nr) F::store_v(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
       }
     }
   }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::store_v(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::store_v(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, part[0][r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::store_v(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
         F::load_v(pin[r], Vp, site, v);
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-        if (r < nr) F::store_v(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
       }
     }
   }
