@@ -46,6 +46,8 @@ struct StepConfig {
   int block;     // threads per workgroup (xy sites per tile)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile
+  int nt;        // 1: nontemporal output stores (pays when a step's working set exceeds the
+                 // Infinity Cache; costs when the next step could have re-read it from there)
 };
 
 // psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).

@@ -99,7 +99,7 @@ __device__ __forceinline__ int find_group(const StepGroup* __restrict__ groups, 
 
 // Variant 0: each thread owns one (x, y) site of the tile and walks the tile's
 // z planes; every neighbour value comes through L1/L2.
-template <int P, int R>
+template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__ groups, int n_groups,
                                                    int tile_base, int n_tiles, int tz,
                                                    const char* __restrict__ in, char* __restrict__ out,
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
         F::load_v(pin[r], Vp, site, v);
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
       }
     }
   }
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
 // Variant 1: as variant 0, but each thread keeps the colour vectors of planes
 // z-2 .. z+2 in a register ring while it marches up the tile's z range, so the
 // z hops and the centre term read no memory; one new plane is loaded per step.
-template <int P, int R>
+template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__ groups, int n_groups,
                                                    int tile_base, int n_tiles, int tz,
                                                    const char* __restrict__ in, char* __restrict__ out,
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
 // z chunks march up and odd chunks march down: two neighbouring chunks reach
 // the planes they share at the same time, so those halo planes are still in
 // L2 for the second reader.
-template <int P, int R>
+template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ groups, int n_groups,
                                                   int tile_base, int n_tiles, int tz,
                                                   const char* __restrict__ in, char* __restrict__ out,
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -462,7 +462,7 @@ __device__ __forceinline__ void inplane_hops(const char* const (&Wmu)[3], const 
 // they come from L2.  Those partial sums wait in a ring for two steps; at
 // plane z the two z hops (W_z from a register ring) and the axpy complete
 // the site.  Chunks alternate their march direction as in variant 2.
-template <int P, int R>
+template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__ groups, int n_groups,
                                                    int tile_base, int n_tiles, int tz,
                                                    const char* __restrict__ in, char* __restrict__ out,
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, part[0][r][c], alpha * ring[2][r][c]);
-        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
 // time.  Fewer registers allow more waves per SIMD, which hide the memory
 // latency of each direction and overlap one wave's arithmetic with the
 // others' loads.
-template <int P, int R>
+template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__ groups, int n_groups,
                                                    int tile_base, int n_tiles, int tz,
                                                    const char* __restrict__ in, char* __restrict__ out,
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
         F::load_v(pin[r], Vp, site, v);
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-        if (r < nr) F::template store_v<real, true>(pout[r], Vp, site, o);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
       }
     }
   }
@@ -849,43 +849,38 @@ __global__ void compare_kernel(const uint4* __restrict__ a, const uint4* __restr
   if (diff) *flag = 1;
 }
 
-template <int P, int R>
-hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+template <int P, int R, bool NT>
+hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
                          int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
   using real = typename Fmt<P>::real;
   const int grid = cfg.grid > 0 ? std::min(cfg.grid, n_tiles) : n_tiles;
-  if (cfg.variant == 0) {
-    step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
-                                                 (real)alpha, (real)beta);
-  } else if (cfg.variant == 1) {
-    // FP64 with three or more RHS would spill the ring: the direct kernel computes the same bits
-    if (P == F64 && R > 2)
-      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
-                                                   (real)alpha, (real)beta);
-    else
-      step_zmarch<P, (P == F64 && R > 2) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
-                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
-  } else if (cfg.variant == 2) {
-    if (P == F64 && R > 1)
-      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
-                                                   (real)alpha, (real)beta);
-    else
-      step_zring<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
-                                                                            cfg.tz, in, out, (real)alpha, (real)beta);
-  } else if (cfg.variant == 4) {
-    step_rolled<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
-                                                 (real)alpha, (real)beta);
-  } else if (cfg.variant == 3) {
-    if (P == F64 && R > 1)
-      step_direct<P, R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
-                                                   (real)alpha, (real)beta);
-    else
-      step_zfront<P, (P == F64 && R > 1) ? 1 : R><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles,
-                                                                             cfg.tz, in, out, (real)alpha, (real)beta);
-  } else {
+  // The ring kernels are instantiated only where their registers fit; FP64 with wider
+  // groups runs the direct kernel, which computes the same bits.
+  const bool direct = cfg.variant == 0 || (P == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4);
+  constexpr int R1 = (P == F64 && R > 2) ? 1 : R;
+  constexpr int R2 = (P == F64) ? 1 : R;
+  const real a = (real)alpha, b = (real)beta;
+  if (direct)
+    step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 1)
+    step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 2)
+    step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 3)
+    step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 4)
+    step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else
     return hipErrorInvalidValue;
-  }
   return hipGetLastError();
+}
+
+template <int P, int R>
+hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+  if (cfg.nt)
+    return launch_step_n<P, R, true>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+  return launch_step_n<P, R, false>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
 }
 
 template <int P>

@@ -220,7 +220,7 @@ struct tl_plan {
 
   std::vector<StepGroup> groups_host;
   int n_tiles = 0;
-  StepConfig cfg{0, 256, 4, 0};
+  StepConfig cfg{0, 256, 4, 0, 0};
   bool ready = false;                   // tuning done (or not requested) and table uploaded
 
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -326,15 +326,14 @@ int plan_autotune(tl_plan* p) {
   }
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
-  for (int variant : {0, 1, 2, 3, 4})
-    for (int block : {256, 128, 64})
-      for (int tz : {1, 2, 4, 8, 16, 32}) {
-        if ((variant == 0 || variant == 4) && tz > 16) continue;
-        if (variant >= 1 && variant <= 3 && tz < 4) continue;   // the z rings pay off over several planes
-        if (variant == 1 && p->prec == TL_F64 && p->width > 2) continue;
-        if ((variant == 2 || variant == 3) && p->prec == TL_F64 && p->width > 1) continue;
-        for (int occ : {0, 4, 8, 16}) cands.push_back({variant, block, tz, occ ? occ * cu : 0});
-      }
+  for (int variant : {0, 2, 3, 4}) {
+    if ((variant == 2 || variant == 3) && p->prec == TL_F64 && p->width > 1) continue;   // would run variant 0
+    const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4} : std::vector<int>{8, 16, 32};
+    for (int block : {256, 64})
+      for (int tz : tzs)
+        for (int grid : {0, 8 * cu})
+          for (int nt : {0, 1}) cands.push_back({variant, block, tz, grid, nt});
+  }
   void* ref = nullptr;
   void* flag_mem = nullptr;
   TL_TRY(dev_alloc(c, &ref, p->buf_bytes));
@@ -380,8 +379,8 @@ int plan_autotune(tl_plan* p) {
       same = one == 0;
     }
     if (c->log)
-      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d: %.4f ms/step%s\n", key.c_str(),
-              p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, ms / reps,
+      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d: %.4f ms/step%s\n",
+              key.c_str(), p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, p->cfg.nt, ms / reps,
               same ? "" : "  OUTPUT DIFFERS - rejected");
     if (same && ms < best) {
       best = ms;
@@ -399,13 +398,16 @@ int plan_autotune(tl_plan* p) {
   return plan_upload_groups(p, p->cfg);
 }
 
-// TL_TILE="variant,block,tz,grid" fixes the step configuration of every plan
+// TL_TILE="variant,block,tz,grid[,nt]" fixes the step configuration of every plan
 // (no tuning): used to profile or sweep one tiling at a time.
 bool tile_override(StepConfig* cfg) {
   const char* e = getenv("TL_TILE");
   if (!e) return false;
   StepConfig c{};
-  if (sscanf(e, "%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid) != 4) return false;
+  const int n = sscanf(e, "%d,%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid, &c.nt);
+  if (n < 4) return false;
+  if (n == 4) c.nt = 0;
+  if (c.nt != 0 && c.nt != 1) return false;
   if (c.variant < 0 || c.variant > 4 || c.block < 64 || c.block > 256 || c.block % 64 || c.tz < 1) return false;
   *cfg = c;
   return true;
@@ -598,7 +600,7 @@ int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_sl
   char* s = nullptr;
   TL_TRY(ctx_scratch(c, 1024 + 2 * fb, &s));
   StepGroup sg{};
-  StepConfig cfg{0, 256, 4, 0};
+  StepConfig cfg{0, 256, 4, 0, 0};
   sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[prec];
   sg.w_mu_stride = Vp * tl::kWBytes[prec];
   sg.psi_off = 0;
@@ -870,6 +872,7 @@ int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
   info->block = p->cfg.block;
   info->tz = p->cfg.tz;
   info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
+  info->nt = p->cfg.nt;
   return TL_OK;
 }
 

@@ -164,7 +164,7 @@ def test_smear_modes_bit_identical(ctx, orc, torch):
 
 VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "1,128,5,512", "2,64,4,0", "2,128,3,0",
                  "2,192,16,256", "2,64,1,8", "3,64,1,0", "3,64,2,0", "3,128,5,0", "3,256,16,0", "3,64,4,8",
-                 "4,64,1,0", "4,256,3,16", "4,128,2,0"]
+                 "4,64,1,0", "4,256,3,16", "4,128,2,0", "2,64,16,0,1", "0,64,2,0,1", "4,64,2,0,1"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
