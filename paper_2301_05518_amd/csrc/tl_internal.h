@@ -32,6 +32,7 @@ struct StepGroup {
   int32_t n_xy_tiles;     // ceil(Lx*Ly / block)
   int32_t n_z_tiles;      // ceil(Lz / tz)
   int32_t tile_begin;     // work-list index of the group's first tile
+  int32_t rows;           // variant 5 only: full rows of the xy plane per tile (divides Ly)
 };
 
 // Launch configuration of the step kernel.
@@ -43,17 +44,36 @@ struct StepConfig {
                  // 3: as 2, with each plane's in-plane hops computed when the plane is
                  //    first loaded (every plane read from memory once)
                  // 4: as 0 with the direction loop rolled (fewer registers, more waves)
-  int block;     // threads per workgroup (xy sites per tile)
+                 // 5: as 2, with tiles of full rows whose in-plane neighbours are
+                 //    exchanged through LDS (fewer vector-memory instructions)
+  int block;     // threads per workgroup (xy sites per tile; variant 5: an upper bound)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile
   int nt;        // 1: nontemporal output stores (pays when a step's working set exceeds the
                  // Infinity Cache; costs when the next step could have re-read it from there)
 };
 
+// Rows per tile of variant 5 for an Lx x Ly plane and a block size: the largest divisor of Ly
+// with rows * Lx <= block and rows >= 4 (0 if there is none).
+inline int lds_rows(int Lx, int Ly, int block) {
+  for (int r = block / Lx; r >= 4; r--)
+    if (Ly % r == 0) return r;
+  return 0;
+}
+
+// Dynamic LDS bytes variant 5 needs for a group: two buffers of (rows + 4) rows of R vectors.
+inline int64_t lds_bytes(int prec, int R, int Lx, int rows) {
+  return 2LL * (rows + 4) * Lx * R * 6 * (prec == F64 ? 8 : 4);
+}
+
 // psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).
+// Raise the dynamic-LDS limit of the LDS-staged step kernels (once per device, before any capture).
+hipError_t init_kernel_attributes();
+
+// lds: dynamic LDS bytes for variant 5 (max over the groups), 0 otherwise.
 hipError_t launch_step(int prec, int width, const StepConfig& cfg, const StepGroup* groups,
                        int n_groups, int tile_base, int n_tiles, const char* in, char* out,
-                       double alpha, double beta, hipStream_t stream);
+                       double alpha, double beta, int64_t lds, hipStream_t stream);
 
 // W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1.
 hipError_t launch_build(int prec, const void* U, const int32_t L[4], int t_first, int slot_first, int n,

@@ -640,6 +640,178 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
   }
 }
 
+template <typename T> struct Complex2;
+template <> struct Complex2<float> { using type = float2; };
+template <> struct Complex2<double> { using type = double2; };
+
+// Variant 5: z-marching as variant 2 (register rings of colour vectors and z
+// two-links, alternating chunk directions) on tiles of `rows` full rows of the
+// xy plane.  Each step every thread publishes its current-plane colour vectors
+// to LDS and the first 4*Lx threads load the four halo rows (two above, two
+// below, periodic); all in-plane neighbours are then read from LDS.  Two LDS
+// buffers alternate by step, so one barrier per step suffices.  Threads past
+// the tile's rows only help with the barrier and the halo.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ groups, int n_groups,
+                                                 int tile_base, int n_tiles, int tz,
+                                                 const char* __restrict__ in, char* __restrict__ out,
+                                                 typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  using c2 = typename Complex2<real>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  c2* const lds = reinterpret_cast<c2*>(lds_raw);
+  const TileSweep sw = xcd_sweep(n_tiles);
+  int it = 0;   // steps done by this workgroup: selects the LDS buffer across tiles
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int y0 = (local - tzi * g.n_xy_tiles) * rows;
+    const int LxLy = Lx * Ly;
+    const int t = (int)threadIdx.x;
+    const int trow = t / Lx, x = t - trow * Lx;
+    const bool active = trow < rows;
+    const int row = active ? trow : 0;
+    const int y = y0 + row;
+    const int xy = y * Lx + x;
+    const int xbw = y * Lx + wrap_step(x, -2, Lx);
+    const int ybw = wrap_step(y, -2, Ly) * Lx + x;
+    const int nsite = (rows + 4) * Lx;
+    const int own = (row + 2) * Lx + x;
+    const int sxf = (row + 2) * Lx + wrap_step(x, 2, Lx), sxb = (row + 2) * Lx + wrap_step(x, -2, Lx);
+    const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
+    const bool halo = t < 4 * Lx;
+    const int hr = halo ? trow : 0;
+    const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;          // halo row relative to y0
+    const int hxy = wrap_step(y0, hrho, Ly) * Lx + x;
+    const int hslot = (hrho + 2) * Lx + x;
+    const char* const Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;
+    real ring[5][R][6];
+    real wz[3][18];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
+      F::load_w(Wmu[2], Vp, zo, wz[k]);
+    }
+    for (int i = 0; i < nz; i++, it++) {
+      const int z = zs + dz * i;
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      {
+        const int64_t za = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy + xy;
+#pragma unroll
+        for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, za, ring[4][r]);
+        const int64_t zw = up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+        F::load_w(Wmu[2], Vp, zw, wz[2]);
+      }
+      c2* const buf = lds + (int64_t)(it & 1) * (R * 3) * nsite;
+      if (halo) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real hv[6];
+          F::load_v(pin[r], Vp, zo + hxy, hv);
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[2 * c], hv[2 * c + 1]};
+        }
+      }
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[2][r][2 * c], ring[2][r][2 * c + 1]};
+      }
+      __syncthreads();
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        const int sf = mu == 0 ? sxf : syf, sb = mu == 0 ? sxb : syb;
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const c2 w = buf[(r * 3 + c) * nsite + sf];
+            v[2 * c] = w.x;
+            v[2 * c + 1] = w.y;
+          }
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wmu[mu], Vp, zo + (mu == 0 ? xbw : ybw), m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const c2 w = buf[(r * 3 + c) * nsite + sb];
+            v[2 * c] = w.x;
+            v[2 * c + 1] = w.y;
+          }
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++) mv_acc(wz[2], ring[4][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++) mdv_acc(wz[0], ring[0][r], acc[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) mv_acc(wz[0], ring[0][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++) mdv_acc(wz[2], ring[4][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (active && r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ build
 
 // W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in precision P.  One thread per site.
@@ -849,14 +1021,18 @@ __global__ void compare_kernel(const uint4* __restrict__ a, const uint4* __restr
   if (diff) *flag = 1;
 }
 
+constexpr int kMaxLds = 160 * 1024;   // LDS per compute unit on gfx950
+
 template <int P, int R, bool NT>
 hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
-                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
   using real = typename Fmt<P>::real;
   const int grid = cfg.grid > 0 ? std::min(cfg.grid, n_tiles) : n_tiles;
   // The ring kernels are instantiated only where their registers fit; FP64 with wider
   // groups runs the direct kernel, which computes the same bits.
   const bool direct = cfg.variant == 0 || (P == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4);
+  (void)lds;
   constexpr int R1 = (P == F64 && R > 2) ? 1 : R;
   constexpr int R2 = (P == F64) ? 1 : R;
   const real a = (real)alpha, b = (real)beta;
@@ -870,43 +1046,70 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
     step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
   else if (cfg.variant == 4)
     step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
-  else
+  else if (cfg.variant == 5) {
+    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+    step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                             a, b);
+  } else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <int P, int R>
 hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
-                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
   if (cfg.nt)
-    return launch_step_n<P, R, true>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
-  return launch_step_n<P, R, false>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    return launch_step_n<P, R, true>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+  return launch_step_n<P, R, false>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+}
+
+template <int P, int R>
+hipError_t allow_lds() {
+  for (const void* f : {reinterpret_cast<const void*>(&step_zlds<P, R, false>),
+                        reinterpret_cast<const void*>(&step_zlds<P, R, true>)}) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int P>
 hipError_t launch_step_p(int width, const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
-                         int n_tiles, const char* in, char* out, double alpha, double beta, hipStream_t s) {
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
   switch (width) {
-    case 1: return launch_step_t<P, 1>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
-    case 2: return launch_step_t<P, 2>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
-    case 3: return launch_step_t<P, 3>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
-    case 4: return launch_step_t<P, 4>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, s);
+    case 1: return launch_step_t<P, 1>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 2: return launch_step_t<P, 2>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 3: return launch_step_t<P, 3>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 4: return launch_step_t<P, 4>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
+hipError_t init_kernel_attributes() {
+  hipError_t e = hipSuccess;
+  for (hipError_t r : {allow_lds<F64, 1>(), allow_lds<F32, 1>(), allow_lds<F32, 2>(), allow_lds<F32, 3>(),
+                       allow_lds<F32, 4>(), allow_lds<F16S, 1>(), allow_lds<F16S, 2>(), allow_lds<F16S, 3>(),
+                       allow_lds<F16S, 4>(), allow_lds<BF16, 1>(), allow_lds<BF16, 2>(), allow_lds<BF16, 3>(),
+                       allow_lds<BF16, 4>()})
+    if (r != hipSuccess) e = r;
+  return e;
+}
+
 hipError_t launch_step(int prec, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
-                       int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
+                       int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
                        hipStream_t stream) {
   if (n_tiles <= 0) return hipSuccess;
-  if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 != 0 || cfg.tz < 1) return hipErrorInvalidValue;
+  const int max_block = cfg.variant == 5 ? 512 : 256;
+  if (cfg.block < 64 || cfg.block > max_block || cfg.block % 64 != 0 || cfg.tz < 1) return hipErrorInvalidValue;
   switch (prec) {
-    case F64: return launch_step_p<F64>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
-    case F32: return launch_step_p<F32>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
-    case F16S: return launch_step_p<F16S>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
-    case BF16: return launch_step_p<BF16>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, stream);
+    case F64: return launch_step_p<F64>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
+    case F32: return launch_step_p<F32>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
+    case F16S: return launch_step_p<F16S>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
+    case BF16: return launch_step_p<BF16>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -32,6 +32,7 @@ struct tl_ctx {
   bool log = false;
   bool fault_alloc = false;   // TL_FAULT=alloc: internal allocations report failure
   bool fault_launch = false;  // TL_FAULT=launch: launches report failure without running
+  bool big_lds = false;       // dynamic-LDS limit raised for the LDS-staged step kernels
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   std::map<std::string, StepConfig> tune;  // tuned step configurations by workload key
@@ -220,6 +221,7 @@ struct tl_plan {
 
   std::vector<StepGroup> groups_host;
   int n_tiles = 0;
+  int64_t lds = 0;                      // dynamic LDS bytes of the step launch (variant 5)
   StepConfig cfg{0, 256, 4, 0, 0};
   bool ready = false;                   // tuning done (or not requested) and table uploaded
 
@@ -248,7 +250,14 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
     s.Lz = g.L[2];
     s.Vp = (int32_t)jc.Vp;
     s.nr = gr.nr;
-    s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
+    if (cfg.variant == 5) {
+      s.rows = tl::lds_rows(g.L[0], g.L[1], cfg.block);
+      if (s.rows == 0) return TL_ERR_UNSUPPORTED;
+      s.n_xy_tiles = g.L[1] / s.rows;
+    } else {
+      s.rows = 0;
+      s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
+    }
     s.n_z_tiles = (g.L[2] + cfg.tz - 1) / cfg.tz;
     s.tile_begin = tiles;
     const int64_t nt = (int64_t)s.n_xy_tiles * s.n_z_tiles;
@@ -259,9 +268,23 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
   return TL_OK;
 }
 
+// Dynamic LDS bytes of a configuration (variant 5), -1 if it does not fit.
+int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<StepGroup>& gs) {
+  if (cfg.variant != 5) return 0;
+  int64_t mx = 0;
+  const int R = (p->prec == TL_F64) ? 1 : p->width;
+  for (const auto& g : gs) mx = std::max(mx, tl::lds_bytes(p->prec, R, g.Lx, g.rows));
+  return mx <= 160 * 1024 ? mx : -1;
+}
+
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
   std::vector<StepGroup> gs;
-  if (make_groups(p, cfg, &gs) != TL_OK) return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list too long");
+  if (make_groups(p, cfg, &gs) != TL_OK)
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list too long, or tiling not applicable to these lattices");
+  const int64_t lds = plan_lds(p, cfg, gs);
+  if (lds < 0 || (lds > 0 && !p->ctx->big_lds))
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "tiling needs more LDS than this device allows");
+  p->lds = lds;
   TL_TRY(upload(p->ctx, p->groups_dev, gs.data(), gs.size() * sizeof(StepGroup)));
   p->groups_host = gs;
   p->n_tiles = gs.empty() ? 0 : gs.back().tile_begin + gs.back().n_xy_tiles * gs.back().n_z_tiles;
@@ -278,7 +301,7 @@ int plan_step(tl_plan* p, hipStream_t s, int parity, int g) {
   }
   return launch(c, "smearing step", [&] {
     return tl::launch_step(p->prec, p->width, p->cfg, p->groups_dev, (int)p->groups_host.size(), base, n,
-                           p->buf[parity], p->buf[parity ^ 1], p->alpha, p->beta, s);
+                           p->buf[parity], p->buf[parity ^ 1], p->alpha, p->beta, p->lds, s);
   });
 }
 
@@ -326,10 +349,12 @@ int plan_autotune(tl_plan* p) {
   }
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
-  for (int variant : {0, 2, 3, 4}) {
-    if ((variant == 2 || variant == 3) && p->prec == TL_F64 && p->width > 1) continue;   // would run variant 0
+  for (int variant : {0, 2, 3, 4, 5}) {
+    if ((variant == 2 || variant == 3 || variant == 5) && p->prec == TL_F64 && p->width > 1) continue;   // would run variant 0
+    if (variant == 5 && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4} : std::vector<int>{8, 16, 32};
-    for (int block : {256, 64})
+    const std::vector<int> blocks = variant == 5 ? std::vector<int>{512, 256} : std::vector<int>{256, 64};
+    for (int block : blocks)
       for (int tz : tzs)
         for (int grid : {0, 8 * cu})
           for (int nt : {0, 1}) cands.push_back({variant, block, tz, grid, nt});
@@ -350,6 +375,10 @@ int plan_autotune(tl_plan* p) {
   const int reps = 5;
   for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
     p->cfg = cands[ci];
+    if (p->cfg.variant == 5) {   // only where every lattice has a row tiling that fits in LDS
+      std::vector<StepGroup> gs;
+      if (make_groups(p, p->cfg, &gs) != TL_OK || plan_lds(p, p->cfg, gs) < 0) continue;
+    }
     rc = plan_upload_groups(p, p->cfg);
     if (rc != TL_OK) break;
     const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
@@ -408,7 +437,7 @@ bool tile_override(StepConfig* cfg) {
   if (n < 4) return false;
   if (n == 4) c.nt = 0;
   if (c.nt != 0 && c.nt != 1) return false;
-  if (c.variant < 0 || c.variant > 4 || c.block < 64 || c.block > 256 || c.block % 64 || c.tz < 1) return false;
+  if (c.variant < 0 || c.variant > 5 || c.block < 64 || c.block > (c.variant == 5 ? 512 : 256) || c.block % 64 || c.tz < 1) return false;
   *cfg = c;
   return true;
 }
@@ -499,6 +528,13 @@ int tl_create(tl_ctx** out, int device, void* stream) {
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
     delete c;
     return fail(nullptr, TL_ERR_DEVICE, "hipGetDeviceProperties(%d) failed", device);
+  }
+  {
+    // the LDS-staged step kernels need more than the default dynamic-LDS limit;
+    // without it their tilings are simply not offered
+    DeviceGuard dg(device);
+    c->big_lds = tl::init_kernel_attributes() == hipSuccess;
+    (void)hipGetLastError();
   }
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
@@ -624,7 +660,7 @@ int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_sl
   char* B = A + fb;
   TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(prec, in, A, offdev, 1, V3, Vp, c->stream); }));
   TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(prec, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, -1.5, 0.25,
-                                      c->stream); }));
+                                      0, c->stream); }));
   return launch(c, "unpack", [&] { return tl::launch_unpack(prec, B, out, offdev, 1, V3, Vp, c->stream); });
 }
 
