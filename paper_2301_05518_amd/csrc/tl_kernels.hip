@@ -1031,7 +1031,11 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   const int grid = cfg.grid > 0 ? std::min(cfg.grid, n_tiles) : n_tiles;
   // The ring kernels are instantiated only where their registers fit; FP64 with wider
   // groups runs the direct kernel, which computes the same bits.
-  const bool direct = cfg.variant == 0 || (P == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4);
+  // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
+  // never selects it for FP64 groups wider than one RHS)
+  if (cfg.variant == 5 && P == F64 && R > 1) return hipErrorInvalidValue;
+  const bool direct = cfg.variant == 0 || (P == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
+                                           cfg.variant != 5);
   (void)lds;
   constexpr int R1 = (P == F64 && R > 2) ? 1 : R;
   constexpr int R2 = (P == F64) ? 1 : R;

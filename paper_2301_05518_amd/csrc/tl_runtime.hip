@@ -278,6 +278,8 @@ int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<Step
 }
 
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
+  if (cfg.variant == 5 && p->prec == TL_F64 && p->width > 1)
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernel takes FP64 groups of one RHS only");
   std::vector<StepGroup> gs;
   if (make_groups(p, cfg, &gs) != TL_OK)
     return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list too long, or tiling not applicable to these lattices");

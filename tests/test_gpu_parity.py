@@ -181,16 +181,41 @@ def test_step_variants_bit_identical(ctx, orc, torch, prec, monkeypatch):
         psi = synth.random_field(rng(25 + k), (len(ts), L[2], L[1], L[0], 3))
         lats.append((L, U, ts, psi))
     outs = {}
-    for tile in VARIANT_TILES:
+    # the LDS-staged kernel takes FP64 groups of one RHS only (these lattices have wider groups)
+    tiles = [t for t in VARIANT_TILES if not (prec == "f64" and t.startswith("5,"))]
+    for tile in tiles:
         monkeypatch.setenv("TL_TILE", tile)
+        log(f"variants {prec}: tile {tile}")
         outs[tile] = gpu_smear(ctx, lats, 7, 2.5, prec)
-    for tile in VARIANT_TILES:
+    for tile in tiles:
         for a, b in zip(outs[tile], outs[VARIANT_TILES[0]]):
             assert np.array_equal(a, b), tile
     for (L, U, ts, psi), o in zip(lats, outs[VARIANT_TILES[0]]):
         ref = orc.smear_batch(orc.build_twolinks(U), ts, 7, 2.5, psi)
         mr, l2 = errors(o, ref)
         assert mr < tol(prec, 7) and l2 < tol(prec, 7)
+
+
+def test_lds_variant_fp64_single_rhs(ctx, orc, torch, monkeypatch):
+    """The LDS-staged kernel at FP64 (groups of one RHS) matches the direct kernel bit for bit;
+    forcing it on a wider FP64 group is refused before any launch."""
+    import paper_2301_05518_amd as tl
+    lats = []
+    for k, (L, ts) in enumerate((((12, 8, 10, 2), [0, 1]), ((6, 5, 7, 1), [0]))):
+        U = haar(L, 27 + k)
+        psi = synth.random_field(rng(27 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+    outs = []
+    for tile in ("0,64,1,0", "5,512,4,0", "5,256,16,8,1"):
+        monkeypatch.setenv("TL_TILE", tile)
+        outs.append(gpu_smear(ctx, lats, 6, 2.0, "f64"))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    monkeypatch.setenv("TL_TILE", "5,512,4,0")
+    L = (12, 8, 10, 1)
+    with pytest.raises(tl.TwolinkError, match="TL_ERR_UNSUPPORTED"):
+        gpu_smear(ctx, [(L, haar(L, 29), [0, 0], synth.random_field(rng(29), (2, 10, 8, 12, 3)))], 6, 2.0, "f64")
 
 
 def test_smear_uneven_batch_fp64(ctx, orc, torch):
