@@ -238,4 +238,178 @@ template <> struct Fmt<BF16> {
   }
 };
 
+
+// ------------------------------------------------------------------ plane pointers
+// The same formats addressed through per-plane base pointers computed once per
+// tile: every load is then a uniform 64-bit base plus a 32-bit site offset
+// (site indices are below 2^27), which the compiler turns into scalar-base +
+// vector-offset loads with no per-load 64-bit arithmetic.
+
+template <int P> struct Planes;
+
+template <> struct Planes<F64> {
+  static constexpr int NW = 9, NV = 3;
+  static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) pl[k] = b + 16 * Vp * k;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      const double2 v = *reinterpret_cast<const double2*>(pl[k] + i * 16u);
+      m[2 * k] = (T)v.x;
+      m[2 * k + 1] = (T)v.y;
+    }
+  }
+  template <typename C>
+  static __device__ __forceinline__ void v(C* b, int64_t Vp, C* (&pl)[NV]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) pl[k] = b + 16 * Vp * k;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const double2 w = *reinterpret_cast<const double2*>(pl[c] + i * 16u);
+      v[2 * c] = (T)w.x;
+      v[2 * c + 1] = (T)w.y;
+    }
+  }
+  template <typename T, bool NT>
+  static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) put<NT>(reinterpret_cast<v2d*>(pl[c] + i * 16u), v2d{(double)v[2 * c], (double)v[2 * c + 1]});
+  }
+};
+
+template <> struct Planes<F32> {
+  static constexpr int NW = 5, NV = 2;
+  static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
+#pragma unroll
+    for (int k = 0; k < 5; k++) pl[k] = b + 16 * Vp * k;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const float4 v = *reinterpret_cast<const float4*>(pl[k] + i * 16u);
+      m[4 * k] = v.x;
+      m[4 * k + 1] = v.y;
+      m[4 * k + 2] = v.z;
+      m[4 * k + 3] = v.w;
+    }
+    const float2 v = *reinterpret_cast<const float2*>(pl[4] + i * 8u);
+    m[16] = v.x;
+    m[17] = v.y;
+  }
+  template <typename C>
+  static __device__ __forceinline__ void v(C* b, int64_t Vp, C* (&pl)[NV]) {
+    pl[0] = b;
+    pl[1] = b + 16 * Vp;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
+    const float4 a = *reinterpret_cast<const float4*>(pl[0] + i * 16u);
+    const float2 c = *reinterpret_cast<const float2*>(pl[1] + i * 8u);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y;
+  }
+  template <typename T, bool NT>
+  static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
+    put<NT>(reinterpret_cast<v4f*>(pl[0] + i * 16u), v4f{(float)v[0], (float)v[1], (float)v[2], (float)v[3]});
+    put<NT>(reinterpret_cast<v2f*>(pl[1] + i * 8u), v2f{(float)v[4], (float)v[5]});
+  }
+};
+
+template <> struct Planes<F16S> {
+  static constexpr int NW = 3, NV = 1;
+  static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
+    pl[0] = b;
+    pl[1] = b + 16 * Vp;
+    pl[2] = b + 32 * Vp;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
+    const uint4 p1 = *reinterpret_cast<const uint4*>(pl[1] + i * 16u);
+    const uint2 p2 = *reinterpret_cast<const uint2*>(pl[2] + i * 8u);
+    const float s = __uint_as_float(p2.y);
+    const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      m[2 * k] = h_to_f32(w[k] & 0xffffu) * s;
+      m[2 * k + 1] = h_to_f32(w[k] >> 16) * s;
+    }
+  }
+  template <typename C>
+  static __device__ __forceinline__ void v(C* b, int64_t Vp, C* (&pl)[NV]) {
+    (void)Vp;
+    pl[0] = b;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
+    const uint4 p = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
+    const float s = __uint_as_float(p.w);
+    v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
+    v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
+    v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
+  }
+  template <typename T, bool NT>
+  static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
+    float f[6];
+    float mx = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      f[c] = (float)v[c];
+      mx = fmaxf(mx, fabsf(f[c]));
+    }
+    // same encoding as Fmt<F16S>::store_v (2^64 pre-scaling of subnormal maxima)
+    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
+    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) f[c] = (f[c] * pre) * inv;
+    put<NT>(reinterpret_cast<v4u*>(pl[0] + i * 16u),
+            v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
+  }
+};
+
+template <> struct Planes<BF16> {
+  static constexpr int NW = 3, NV = 2;
+  static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
+    pl[0] = b;
+    pl[1] = b + 16 * Vp;
+    pl[2] = b + 32 * Vp;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
+    const uint4 p1 = *reinterpret_cast<const uint4*>(pl[1] + i * 16u);
+    const uint32_t p2 = *reinterpret_cast<const uint32_t*>(pl[2] + i * 4u);
+    const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2};
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      m[2 * k] = bf16_to_f32(w[k] & 0xffffu);
+      m[2 * k + 1] = bf16_to_f32(w[k] >> 16);
+    }
+  }
+  template <typename C>
+  static __device__ __forceinline__ void v(C* b, int64_t Vp, C* (&pl)[NV]) {
+    pl[0] = b;
+    pl[1] = b + 8 * Vp;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
+    const uint2 p = *reinterpret_cast<const uint2*>(pl[0] + i * 8u);
+    const uint32_t q = *reinterpret_cast<const uint32_t*>(pl[1] + i * 4u);
+    v[0] = bf16_to_f32(p.x & 0xffffu); v[1] = bf16_to_f32(p.x >> 16);
+    v[2] = bf16_to_f32(p.y & 0xffffu); v[3] = bf16_to_f32(p.y >> 16);
+    v[4] = bf16_to_f32(q & 0xffffu);   v[5] = bf16_to_f32(q >> 16);
+  }
+  template <typename T, bool NT>
+  static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
+    put<NT>(reinterpret_cast<v2u*>(pl[0] + i * 8u), v2u{pack_bf16((float)v[0], (float)v[1]), pack_bf16((float)v[2], (float)v[3])});
+    put<NT>(reinterpret_cast<uint32_t*>(pl[1] + i * 4u), pack_bf16((float)v[4], (float)v[5]));
+  }
+};
+
 }  // namespace tl

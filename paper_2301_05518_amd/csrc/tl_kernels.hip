@@ -41,6 +41,15 @@ __device__ __forceinline__ TileSweep xcd_sweep(int n_tiles) {
   return {t0 + j, cnt, t1};
 }
 
+// v mod L for v in [-2L, 3L), branch-free
+__device__ __forceinline__ int wrap_sel(int v, int L) {
+  v = v >= L ? v - L : v;
+  v = v >= L ? v - L : v;
+  v = v < 0 ? v + L : v;
+  v = v < 0 ? v + L : v;
+  return v;
+}
+
 __device__ __forceinline__ int wrap_step(int v, int d, int L) {
   v += d;
   while (v >= L) v -= L;
@@ -650,14 +659,16 @@ template <> struct Complex2<double> { using type = double2; };
 // to LDS and the first 4*Lx threads load the four halo rows (two above, two
 // below, periodic); all in-plane neighbours are then read from LDS.  Two LDS
 // buffers alternate by step, so one barrier per step suffices.  Threads past
-// the tile's rows only help with the barrier and the halo.
+// the tile's rows only help with the barrier and the halo.  Fields are
+// addressed through per-plane base pointers set up once per tile and 32-bit
+// site offsets; plane wraps are branch-free.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ groups, int n_groups,
                                                  int tile_base, int n_tiles, int tz,
                                                  const char* __restrict__ in, char* __restrict__ out,
                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
-  using F = Fmt<P>;
-  using real = typename F::real;
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
   using c2 = typename Complex2<real>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   c2* const lds = reinterpret_cast<c2*>(lds_raw);
@@ -678,26 +689,28 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
     const int row = active ? trow : 0;
     const int y = y0 + row;
     const int xy = y * Lx + x;
-    const int xbw = y * Lx + wrap_step(x, -2, Lx);
-    const int ybw = wrap_step(y, -2, Ly) * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - 2, Lx);
+    const int ybw = wrap_sel(y - 2, Ly) * Lx + x;
     const int nsite = (rows + 4) * Lx;
     const int own = (row + 2) * Lx + x;
-    const int sxf = (row + 2) * Lx + wrap_step(x, 2, Lx), sxb = (row + 2) * Lx + wrap_step(x, -2, Lx);
+    const int sxf = (row + 2) * Lx + wrap_sel(x + 2, Lx), sxb = (row + 2) * Lx + wrap_sel(x - 2, Lx);
     const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
     const bool halo = t < 4 * Lx;
     const int hr = halo ? trow : 0;
     const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;          // halo row relative to y0
-    const int hxy = wrap_step(y0, hrho, Ly) * Lx + x;
+    const int hxy = wrap_sel(y0 + hrho, Ly) * Lx + x;
     const int hslot = (hrho + 2) * Lx + x;
-    const char* const Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const char* wp[3][PL::NW];
+#pragma unroll
+    for (int mu = 0; mu < 3; mu++) PL::w(g.W + mu * g.w_mu_stride, Vp, wp[mu]);
     const int nr = g.nr;
-    const char* pin[R];
-    char* pout[R];
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
-      pin[r] = in + o;
-      pout[r] = out + o;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
     }
     const int zlo = tzi * tz;
     const int nz = min(zlo + tz, Lz) - zlo;
@@ -708,32 +721,30 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
     real wz[3][18];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+      const uint32_t zo = (uint32_t)(wrap_sel(zs + dz * (k - 2), Lz) * LxLy + xy);
 #pragma unroll
-      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zo, ring[k][r]);
+      for (int r = 0; r < R; r++) PL::load_v(ip[r], zo, ring[k][r]);
     }
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-      const int64_t zo = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
-      F::load_w(Wmu[2], Vp, zo, wz[k]);
-    }
+    for (int k = 0; k < 2; k++)
+      PL::load_w(wp[2], (uint32_t)(wrap_sel(zs + (up ? k - 2 : -k), Lz) * LxLy + xy), wz[k]);
     for (int i = 0; i < nz; i++, it++) {
       const int z = zs + dz * i;
-      const int64_t zo = (int64_t)z * LxLy;
-      const int64_t site = zo + xy;
+      const uint32_t zo = (uint32_t)(z * LxLy);
+      const uint32_t site = zo + xy;
       {
-        const int64_t za = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy + xy;
+        const uint32_t za = (uint32_t)(wrap_sel(z + 2 * dz, Lz) * LxLy + xy);
 #pragma unroll
-        for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, za, ring[4][r]);
-        const int64_t zw = up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
-        F::load_w(Wmu[2], Vp, zw, wz[2]);
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], za, ring[4][r]);
+        const uint32_t zw = up ? site : (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy);
+        PL::load_w(wp[2], zw, wz[2]);
       }
-      c2* const buf = lds + (int64_t)(it & 1) * (R * 3) * nsite;
+      c2* const buf = lds + (it & 1) * (R * 3) * nsite;
       if (halo) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
           real hv[6];
-          F::load_v(pin[r], Vp, zo + hxy, hv);
+          PL::load_v(ip[r], zo + hxy, hv);
 #pragma unroll
           for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[2 * c], hv[2 * c + 1]};
         }
@@ -754,7 +765,7 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
       for (int mu = 0; mu < 2; mu++) {
         const int sf = mu == 0 ? sxf : syf, sb = mu == 0 ? sxb : syb;
         real m[18];
-        F::load_w(Wmu[mu], Vp, site, m);
+        PL::load_w(wp[mu], site, m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
           real v[6];
@@ -766,7 +777,7 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
           }
           mv_acc(m, v, acc[r]);
         }
-        F::load_w(Wmu[mu], Vp, zo + (mu == 0 ? xbw : ybw), m);
+        PL::load_w(wp[mu], zo + (uint32_t)(mu == 0 ? xbw : ybw), m);
 #pragma unroll
         for (int r = 0; r < R; r++) {
           real v[6];
@@ -795,7 +806,7 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
         real o[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
-        if (active && r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
       }
 #pragma unroll
       for (int k = 0; k < 4; k++)
