@@ -32,7 +32,7 @@ struct StepGroup {
   int32_t n_xy_tiles;     // ceil(Lx*Ly / block)
   int32_t n_z_tiles;      // ceil(Lz / tz)
   int32_t tile_begin;     // work-list index of the group's first tile
-  int32_t rows;           // variant 5 only: full rows of the xy plane per tile (divides Ly)
+  int32_t rows;           // variants 5, 6: full rows of the xy plane per tile (divides Ly)
 };
 
 // Launch configuration of the step kernel.
@@ -46,6 +46,8 @@ struct StepConfig {
                  // 4: as 0 with the direction loop rolled (fewer registers, more waves)
                  // 5: as 2, with tiles of full rows whose in-plane neighbours are
                  //    exchanged through LDS (fewer vector-memory instructions)
+                 // 6: as 5, marching chains of planes z, z+2, ... (smaller rings; the
+                 //    in-plane two-links are loaded before the LDS barrier)
   int block;     // threads per workgroup (xy sites per tile; variant 5: an upper bound)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile
