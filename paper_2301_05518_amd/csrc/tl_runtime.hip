@@ -382,7 +382,7 @@ int plan_autotune(tl_plan* p) {
   (void)hipEventCreate(&e1);
   float best = 1e30f;
   StepConfig best_cfg = cands[0];
-  const int reps = 5;
+  const int reps = 10;
   for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
     p->cfg = cands[ci];
     if (p->cfg.variant == 5 || p->cfg.variant == 6) {   // only where every lattice has a row tiling that fits in LDS
