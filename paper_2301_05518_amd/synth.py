@@ -248,6 +248,9 @@ def workload(index: int) -> Workload:
        t = 0, 12, ..., 84 (24 RHS), N=60, sigma=6, FP32.
     4: uneven batch 24^3x48 + 32^3x64 + 48^3x96, Haar links, 1/2/4 random
        slices per lattice x 3 colour-diluted Z2 sources, N=40, sigma=4, BF16.
+    5: sink smearing of a whole propagator: 64^3x96, Haar links, 3 colour
+       walls on every one of the 96 slices (288 RHS) with one two-link field
+       for all slices, N=60, sigma=6, FP32.
     """
     s = lambda stream: seed_for(index + 1, stream)  # noqa: E731
     if index == 0:
@@ -277,4 +280,11 @@ def workload(index: int) -> Workload:
             lats.append(Lattice(L, "haar", s(STREAM_LINKS) + 1000 * j, t_of_rhs, srcs,
                                 s(STREAM_SOURCES) + 1000 * (j + 1)))
         return Workload("uneven 24^3x48+32^3x64+48^3x96 bf16 Z2 N=40 sigma=4", lats, 40, 4.0, ("bf16",))
+    if index == 5:
+        ts = list(range(96))
+        t_of_rhs = [t for t in ts for _ in range(3)]
+        srcs = [("wall", c) for _ in ts for c in range(3)]
+        lat = Lattice((64, 64, 64, 96), "haar", s(STREAM_LINKS), t_of_rhs, srcs, s(STREAM_SOURCES))
+        return Workload("64^3x96 fp32 sink smearing: 3 colour walls x 96 slices N=60 sigma=6", [lat], 60, 6.0,
+                        ("f32",))
     raise IndexError(index)
