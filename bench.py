@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--cpu-rhs", type=int, default=24, help="RHS in the CPU oracle sample")
     ap.add_argument("--flags", type=int, default=6, help="plan flags (2 graph | 4 autotune)")
+    ap.add_argument("--w12", action="store_true",
+                    help="twelve-real two-link storage (two rows stored, third rebuilt; SU(3) links)")
     ap.add_argument("--tile", default=None, help="fixed step tiling 'variant,block,tz,grid' (no tuning)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
@@ -56,10 +58,15 @@ def parse():
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("tl_kernels.hip", "tl_format.h", "tl_internal.h"):
+    for f in ("tl_kernels.hip", "tl_step.h", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip",
+              "tl_step_bf16.hip", "tl_format.h", "tl_internal.h"):
         with open(os.path.join(ROOT, "paper_2301_05518_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def workload_key(args) -> str:
+    return f"workload{args.workload}" + ("-w12" if args.w12 else "")
 
 
 def measured_traffic(workload_key: str):
@@ -159,7 +166,7 @@ def cpu_baseline(lat, wl, U_dev, n_rhs_sample):
 def main():
     args = parse()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, f"workload{args.workload}", args.tile)
+        summarize_counters(*args.summarize_counters, workload_key(args), args.tile)
         return
     if args.tile:
         os.environ["TL_TILE"] = args.tile
@@ -175,7 +182,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     wl = synth.workload(args.workload)
-    prec = wl.precisions[0]
+    prec = wl.precisions[0] + ("-w12" if args.w12 else "")
     workers = min(16, os.cpu_count() or 1)
     log(f"[bench] workload {args.workload}: {wl.name}; drawing inputs")
     t_in = time.perf_counter()
@@ -239,7 +246,7 @@ def main():
     info = plan.info()
     step_ms = plan.time(reps=3)
     achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
-    key = f"workload{args.workload}"
+    key = workload_key(args)
     traffic = measured_traffic(key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -313,7 +320,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": wl.precisions[0],
         "data": "synthetic",
         "config": {
             "workload": wl.name,
@@ -322,7 +329,7 @@ def main():
             "n_smear": wl.n_steps,
             "sigma": wl.sigma,
             "storage": prec,
-            "accumulate": "f64" if prec == "f64" else "f32",
+            "accumulate": "f64" if wl.precisions[0] == "f64" else "f32",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
             "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "n_tiles", "group_width")},
         },

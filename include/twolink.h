@@ -41,6 +41,19 @@
  *   three use FP32 arithmetic.  The two-link product is always formed in
  *   FP64 and rounded to the storage precision when stored.  Reductions
  *   accumulate in FP64.
+ * - Twelve-real two-links: every `prec` argument may carry TL_W12
+ *   (e.g. TL_F32 | TL_W12).  The two-link field then stores only the first
+ *   two rows of each W_mu(x) and the kernels rebuild the third as the complex
+ *   conjugate of the cross product of the first two, which is exact for
+ *   special unitary matrices: a two-link of SU(3) links is in SU(3), but
+ *   one of links that are not special unitary (e.g. gauge-smeared links
+ *   without reunitarisation, end of Sec. 2) is not, and for those the
+ *   results are wrong -- the caller guarantees SU(3) links.
+ *   Bytes per site and direction: 96 (F64), 48 (F32), 24 (F16S, BF16; the
+ *   16-bit forms hold plain values with no scale, every entry of an SU(3)
+ *   matrix having modulus <= 1).  Colour vectors keep the format of the
+ *   precision.  A field built with TL_W12 must be used with TL_W12 and the
+ *   same precision.
  */
 #ifndef TWOLINK_H
 #define TWOLINK_H
@@ -65,6 +78,7 @@ enum {
 };
 
 enum { TL_F64 = 0, TL_F32 = 1, TL_F16S = 2, TL_BF16 = 3 };
+enum { TL_W12 = 16 };   /* OR into a precision: twelve-real (two-row) two-link storage */
 
 /* tl_smear / tl_plan_create flags */
 enum {
@@ -145,7 +159,7 @@ const char *tl_last_error(const tl_ctx *ctx);
 
 /* TL_OK if g is a supported geometry, TL_ERR_SHAPE (or TL_ERR_ARG for NULL) otherwise. */
 int tl_check_geom(const tl_geom *g);
-/* Bytes of a two-link field for n_slices slices in precision prec (0 on bad arguments). */
+/* Bytes of a two-link field for n_slices slices in precision prec (optionally | TL_W12; 0 on bad arguments). */
 size_t tl_twolinks_bytes(const tl_geom *g, int prec, int n_slices);
 
 /* ---------------------------------------------------------------- the path */
@@ -153,7 +167,8 @@ size_t tl_twolinks_bytes(const tl_geom *g, int prec, int n_slices);
 /*
  * Two-link product (Sec. 2; precomputed once per gauge field, Sec. 3):
  * W_mu(x) = U_mu(x) U_mu(x+mu^) for mu = x, y, z at every site of the listed
- * slices, formed in FP64 and stored in precision `prec`.
+ * slices, formed in FP64 and stored in precision `prec` (| TL_W12: first two
+ * rows only).
  *   U        device, complex128 natural gauge field of geometry g (only the
  *            spatial links of the listed slices are read)
  *   slices   host, n_slices slice indices, each in [0, Lt), no repeats;

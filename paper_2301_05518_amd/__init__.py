@@ -13,6 +13,10 @@ Layouts (torch tensors on the context's device):
   gauge field U  complex128 [Lt][Lz][Ly][Lx][4][3][3]
   colour vectors complex128 [n_rhs][Lz][Ly][Lx][3]
   two-link field uint8 buffer of ``twolinks_bytes(L, prec, n_slices)`` bytes
+
+Precisions: "f64", "f32", "f16s", "bf16" (colour vectors and two-links), each
+also as "<prec>-w12": two-links stored as their first two rows only (12 reals),
+the third rebuilt in the kernels, valid for SU(3) gauge links only.
 """
 from __future__ import annotations
 
@@ -21,9 +25,9 @@ from dataclasses import dataclass
 from typing import Sequence
 
 from . import _lib
-from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_PLAIN, TwolinkError  # noqa: F401
+from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_PLAIN, TL_W12, TwolinkError  # noqa: F401
 
-__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE",
+__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE", "TL_W12",
            "twolinks_bytes", "library"]
 
 
@@ -44,6 +48,14 @@ def _prec(p) -> int:
             raise ValueError(f"unknown precision {p!r}; one of {list(PREC)}")
         return PREC[p]
     return int(p)
+
+
+def _check_w_format(W, prec, name: str):
+    """A two-link buffer built by Context.build_twolinks remembers its format; a mismatch
+    (other precision, or 12- vs 18-real storage) would be read as garbage."""
+    built = getattr(W, "_tl_prec", None)
+    if built is not None and built != _prec(prec):
+        raise ValueError(f"{name} was built with precision code {built}, used with {_prec(prec)}")
 
 
 def _i32(values):
@@ -148,6 +160,7 @@ class Context:
         self._check(self.lib.tl_build_twolinks(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(U)),
                                                arr, ns if slices is not None else 0, _prec(prec),
                                                ctypes.c_void_p(_ptr(W))))
+        W._tl_prec = _prec(prec)
         return W
 
     def laplacian(self, L, W, prec, t, psi_in, out=None, w_slices=None):
@@ -157,6 +170,7 @@ class Context:
             out = torch.empty_like(psi_in)
         _need(out, "complex128", _v3(L) * 3, "out")
         nw = int(L[3]) if w_slices is None else len(w_slices)
+        _check_w_format(W, prec, "W")
         _need(W, "uint8", twolinks_bytes(L, prec, nw), "W", at_least=True)
         arr, n = _i32(w_slices)
         self._check(self.lib.tl_laplacian(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(W)), arr, n,
@@ -170,6 +184,7 @@ class Context:
         for i, j in enumerate(jobs):
             _need(j.psi, "complex128", len(j.t_of_rhs) * _v3(j.L) * 3, f"jobs[{i}].psi")
             nw = int(j.L[3]) if j.w_slices is None else len(j.w_slices)
+            _check_w_format(j.W, prec, f"jobs[{i}].W")
             _need(j.W, "uint8", twolinks_bytes(j.L, prec, nw), f"jobs[{i}].W", at_least=True)
             ts, nt = _i32(j.t_of_rhs)
             ws, nw = _i32(j.w_slices)

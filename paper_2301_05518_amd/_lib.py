@@ -11,7 +11,9 @@ ERRORS = {
     -1: "TL_ERR_ARG", -2: "TL_ERR_SHAPE", -3: "TL_ERR_PRECISION", -4: "TL_ERR_DEVICE",
     -5: "TL_ERR_HIP", -6: "TL_ERR_NOMEM", -7: "TL_ERR_UNSUPPORTED",
 }
-PREC = {"f64": 0, "f32": 1, "f16s": 2, "bf16": 3}
+TL_W12 = 16   # OR into a precision: twelve-real (two-row) two-link storage
+PREC = {"f64": 0, "f32": 1, "f16s": 2, "bf16": 3,
+        "f64-w12": 0 | TL_W12, "f32-w12": 1 | TL_W12, "f16s-w12": 2 | TL_W12, "bf16-w12": 3 | TL_W12}
 TL_PLAIN, TL_GRAPH, TL_AUTOTUNE = 1, 2, 4
 TL_NORM2, TL_DOT, TL_SITE_NORM = 0, 1, 2
 

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtwolink.so")
-SOURCES = ["tl_kernels.hip", "tl_runtime.hip"]
+SOURCES = ["tl_kernels.hip", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip", "tl_step_bf16.hip",
+           "tl_runtime.hip"]
 ARCH = os.environ.get("TL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -13,6 +13,16 @@
 //              (2 x half, FP32 scale)                        + FP32 scale
 //   BF16       2 planes 8 x bf16 + 1 plane 2 x bf16   36 B   4 x bf16 + 2 x bf16   12 B
 //
+// Twelve-real two-link forms (format code = precision | W12): only the first
+// two rows of each matrix are stored and the third is rebuilt on load as the
+// complex conjugate of the cross product of the first two, which is the third
+// row of any SU(3) matrix (a two-link is a product of two SU(3) links):
+//   FP64|W12   6 planes double2                        96 B
+//   FP32|W12   3 planes float4                         48 B
+//   F16S|W12   1 plane 8 x half + 1 plane 4 x half     24 B   (no scale: every entry
+//   BF16|W12   1 plane 8 x bf16 + 1 plane 4 x bf16     24 B    of an SU(3) matrix is <= 1)
+// Colour vectors keep the format of the precision.
+//
 // F16S stores value / s as IEEE half, with s = max |real| of the site (one
 // scale per site and direction for W, per site and RHS for vectors); s = 0
 // encodes an all-zero site.  Stores round to nearest even.  FP64 values
@@ -63,6 +73,29 @@ template <bool NT, typename V>
 __device__ __forceinline__ void put(V* p, V v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
+}
+
+// Third row of a special unitary 3x3 matrix from its first two rows (m[0..11]):
+// m(2, k) = conj(m(0, j) m(1, l) - m(0, l) m(1, j)) for (k, j, l) cyclic.  The
+// operation order is fixed, so every kernel rebuilds the same bits.
+template <typename T>
+__device__ __forceinline__ void su3_row3(T (&m)[18]) {
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const int j = (k + 1) % 3, l = (k + 2) % 3;
+    const T ajr = m[2 * j], aji = m[2 * j + 1], alr = m[2 * l], ali = m[2 * l + 1];
+    const T bjr = m[6 + 2 * j], bji = m[6 + 2 * j + 1], blr = m[6 + 2 * l], bli = m[6 + 2 * l + 1];
+    T re = ajr * blr;
+    re = fma_(-aji, bli, re);
+    re = fma_(-alr, bjr, re);
+    re = fma_(ali, bji, re);
+    T im = ajr * bli;
+    im = fma_(aji, blr, im);
+    im = fma_(-alr, bji, im);
+    im = fma_(-ali, bjr, im);
+    m[12 + 2 * k] = re;
+    m[12 + 2 * k + 1] = -im;
+  }
 }
 
 template <int P> struct Fmt;
@@ -238,16 +271,109 @@ template <> struct Fmt<BF16> {
   }
 };
 
+// ------------------------------------------------------------------ twelve-real two-links
+
+template <> struct Fmt<F64 | W12> : Fmt<F64> {
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    const double2* p = reinterpret_cast<const double2*>(b);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      double2 v = p[k * Vp + i];
+      m[2 * k] = (T)v.x;
+      m[2 * k + 1] = (T)v.y;
+    }
+    su3_row3(m);
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    double2* p = reinterpret_cast<double2*>(b);
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k * Vp + i] = make_double2(m[2 * k], m[2 * k + 1]);
+  }
+};
+
+template <> struct Fmt<F32 | W12> : Fmt<F32> {
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    const float4* p = reinterpret_cast<const float4*>(b);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      float4 v = p[k * Vp + i];
+      m[4 * k] = v.x;
+      m[4 * k + 1] = v.y;
+      m[4 * k + 2] = v.z;
+      m[4 * k + 3] = v.w;
+    }
+    su3_row3(m);
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    float4* p = reinterpret_cast<float4*>(b);
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+      p[k * Vp + i] = make_float4((float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]);
+  }
+};
+
+// 16-bit twelve-real forms: twelve values in a 16-byte and an 8-byte plane.
+template <uint32_t (*Pack)(float, float), float (*Unpack)(uint32_t)>
+struct Fmt16W12 {
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
+    const uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
+    const uint2 p1 = reinterpret_cast<const uint2*>(b + 16 * Vp)[i];
+    const uint32_t w[6] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      m[2 * k] = Unpack(w[k] & 0xffffu);
+      m[2 * k + 1] = Unpack(w[k] >> 16);
+    }
+    su3_row3(m);
+  }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
+    uint32_t w[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) w[k] = Pack((float)m[2 * k], (float)m[2 * k + 1]);
+    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint2*>(b + 16 * Vp)[i] = make_uint2(w[4], w[5]);
+  }
+};
+
+template <> struct Fmt<F16S | W12> : Fmt<F16S> {
+  using W = Fmt16W12<pack_h, h_to_f32>;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) { W::load_w(b, Vp, i, m); }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) { W::store_w(b, Vp, i, m); }
+};
+
+template <> struct Fmt<BF16 | W12> : Fmt<BF16> {
+  using W = Fmt16W12<pack_bf16, bf16_to_f32>;
+  template <typename T>
+  __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) { W::load_w(b, Vp, i, m); }
+  __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) { W::store_w(b, Vp, i, m); }
+};
 
 // ------------------------------------------------------------------ plane pointers
 // The same formats addressed through per-plane base pointers computed once per
 // tile: every load is then a uniform 64-bit base plus a 32-bit site offset
 // (site indices are below 2^27), which the compiler turns into scalar-base +
 // vector-offset loads with no per-load 64-bit arithmetic.
+// load_w_raw + finish_w split a two-link load so that the arithmetic that
+// completes it (the third row of a twelve-real form) can be placed after a
+// barrier; for the eighteen-real forms finish_w does nothing.
 
 template <int P> struct Planes;
 
-template <> struct Planes<F64> {
+template <class D, int NW_>
+struct FullW {
+  template <typename T>
+  static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW_], uint32_t i, T (&m)[18]) {
+    D::load_w(pl, i, m);
+  }
+  template <typename T>
+  static __device__ __forceinline__ void finish_w(T (&)[18]) {}
+};
+
+template <> struct Planes<F64> : FullW<Planes<F64>, 9> {
   static constexpr int NW = 9, NV = 3;
   static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
 #pragma unroll
@@ -283,7 +409,7 @@ template <> struct Planes<F64> {
   }
 };
 
-template <> struct Planes<F32> {
+template <> struct Planes<F32> : FullW<Planes<F32>, 5> {
   static constexpr int NW = 5, NV = 2;
   static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
 #pragma unroll
@@ -321,7 +447,7 @@ template <> struct Planes<F32> {
   }
 };
 
-template <> struct Planes<F16S> {
+template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
   static constexpr int NW = 3, NV = 1;
   static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
     pl[0] = b;
@@ -373,7 +499,7 @@ template <> struct Planes<F16S> {
   }
 };
 
-template <> struct Planes<BF16> {
+template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
   static constexpr int NW = 3, NV = 2;
   static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
     pl[0] = b;
@@ -411,5 +537,77 @@ template <> struct Planes<BF16> {
     put<NT>(reinterpret_cast<uint32_t*>(pl[1] + i * 4u), pack_bf16((float)v[4], (float)v[5]));
   }
 };
+
+// Twelve-real two-link forms: the plane pointers of rows 0 and 1.
+template <class Base, int NW_>
+struct PlanesW12 : Base {
+  static constexpr int NW = NW_;
+  static __device__ __forceinline__ void w(const char* b, int64_t Vp, const char* (&pl)[NW]) {
+#pragma unroll
+    for (int k = 0; k < NW; k++) pl[k] = b + 16 * Vp * k;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void finish_w(T (&m)[18]) { su3_row3(m); }
+};
+
+template <> struct Planes<F64 | W12> : PlanesW12<Planes<F64>, 6> {
+  template <typename T>
+  static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const double2 v = *reinterpret_cast<const double2*>(pl[k] + i * 16u);
+      m[2 * k] = (T)v.x;
+      m[2 * k + 1] = (T)v.y;
+    }
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    load_w_raw(pl, i, m);
+    finish_w(m);
+  }
+};
+
+template <> struct Planes<F32 | W12> : PlanesW12<Planes<F32>, 3> {
+  template <typename T>
+  static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const float4 v = *reinterpret_cast<const float4*>(pl[k] + i * 16u);
+      m[4 * k] = v.x;
+      m[4 * k + 1] = v.y;
+      m[4 * k + 2] = v.z;
+      m[4 * k + 3] = v.w;
+    }
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    load_w_raw(pl, i, m);
+    finish_w(m);
+  }
+};
+
+template <class Base, float (*Unpack)(uint32_t)>
+struct Planes16W12 : PlanesW12<Base, 2> {
+  static constexpr int NW = 2;
+  template <typename T>
+  static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
+    const uint2 p1 = *reinterpret_cast<const uint2*>(pl[1] + i * 8u);
+    const uint32_t w[6] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      m[2 * k] = Unpack(w[k] & 0xffffu);
+      m[2 * k + 1] = Unpack(w[k] >> 16);
+    }
+  }
+  template <typename T>
+  static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    load_w_raw(pl, i, m);
+    PlanesW12<Base, 2>::finish_w(m);
+  }
+};
+
+template <> struct Planes<F16S | W12> : Planes16W12<Planes<F16S>, h_to_f32> {};
+template <> struct Planes<BF16 | W12> : Planes16W12<Planes<BF16>, bf16_to_f32> {};
 
 }  // namespace tl

@@ -10,11 +10,18 @@ namespace tl {
 // Storage precisions (same values as TL_F64 ... TL_BF16 in twolink.h).
 enum Prec : int { F64 = 0, F32 = 1, F16S = 2, BF16 = 3 };
 
-// Packed two-link field: per slot, per direction mu, per site, kWBytes[prec]
+// Format codes: a precision, or precision | W12 for the twelve-real two-link
+// form (first two rows stored, third rebuilt).  Kernels are templated on the
+// format code; colour vectors always use the format of vprec(code).
+constexpr int W12 = 4;
+constexpr int vprec(int code) { return code & 3; }
+constexpr bool is_w12(int code) { return (code & W12) != 0; }
+
+// Packed two-link field: per slot, per direction mu, per site, kWBytes[code]
 // bytes split into planes of vector words (see tl_format.h).  Packed colour
-// vectors: per right-hand side, per site, kVBytes[prec] bytes, also in planes.
-constexpr int kWBytes[4] = {144, 72, 40, 36};
-constexpr int kVBytes[4] = {48, 24, 16, 12};
+// vectors: per right-hand side, per site, kVBytes[code] bytes, also in planes.
+constexpr int kWBytes[8] = {144, 72, 40, 36, 96, 48, 24, 24};
+constexpr int kVBytes[8] = {48, 24, 16, 12, 48, 24, 16, 12};
 
 // Plane length: sites per plane, rounded up so every plane starts 256-byte aligned.
 inline int64_t padded_sites(int64_t v3) { return (v3 + 63) / 64 * 64; }
@@ -63,22 +70,35 @@ inline int lds_rows(int Lx, int Ly, int block) {
   return 0;
 }
 
-// Dynamic LDS bytes variant 5 needs for a group: two buffers of (rows + 4) rows of R vectors.
-inline int64_t lds_bytes(int prec, int R, int Lx, int rows) {
-  return 2LL * (rows + 4) * Lx * R * 6 * (prec == F64 ? 8 : 4);
+// Dynamic LDS bytes variants 5 and 6 need for a group: two buffers of (rows + 4) rows of R vectors.
+inline int64_t lds_bytes(int code, int R, int Lx, int rows) {
+  return 2LL * (rows + 4) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
 }
 
-// psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).
 // Raise the dynamic-LDS limit of the LDS-staged step kernels (once per device, before any capture).
 hipError_t init_kernel_attributes();
 
-// lds: dynamic LDS bytes for variant 5 (max over the groups), 0 otherwise.
-hipError_t launch_step(int prec, int width, const StepConfig& cfg, const StepGroup* groups,
+// psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).
+// code: format code (precision, optionally | W12).  lds: dynamic LDS bytes for variants 5
+// and 6 (max over the groups), 0 otherwise.
+hipError_t launch_step(int code, int width, const StepConfig& cfg, const StepGroup* groups,
                        int n_groups, int tile_base, int n_tiles, const char* in, char* out,
                        double alpha, double beta, int64_t lds, hipStream_t stream);
 
-// W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1.
-hipError_t launch_build(int prec, const void* U, const int32_t L[4], int t_first, int slot_first, int n,
+// The step kernels of one precision, both two-link forms (one translation unit each).
+#define TL_STEP_DECL(name)                                                                              \
+  hipError_t launch_step_##name(bool w12, int width, const StepConfig& cfg, const StepGroup* groups,     \
+                                int n_groups, int tile_base, int n_tiles, const char* in, char* out,    \
+                                double alpha, double beta, int64_t lds, hipStream_t stream);           \
+  hipError_t step_attributes_##name();
+TL_STEP_DECL(f64)
+TL_STEP_DECL(f32)
+TL_STEP_DECL(f16s)
+TL_STEP_DECL(bf16)
+#undef TL_STEP_DECL
+
+// W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1, in format `code`.
+hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first, int slot_first, int n,
                         void* W, hipStream_t stream);
 
 // Natural complex128 [rhs][V3][3] <-> packed resident field.  rhs_off[r] is

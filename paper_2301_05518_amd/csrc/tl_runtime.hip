@@ -22,6 +22,7 @@ using tl::StepGroup;
 
 static_assert(TL_F64 == tl::F64 && TL_F32 == tl::F32 && TL_F16S == tl::F16S && TL_BF16 == tl::BF16,
               "precision codes");
+static_assert((TL_W12 & 3) == 0, "TL_W12 is a bit above the precision codes");
 
 struct tl_ctx {
   int device = -1;
@@ -83,7 +84,14 @@ struct DeviceGuard {
   }
 };
 
-bool valid_prec(int p) { return p >= TL_F64 && p <= TL_BF16; }
+// Internal format code of a public precision argument (precision, optionally | TL_W12), -1 if invalid.
+int fmt_code(int p) {
+  const int base = p & ~TL_W12;
+  if (base < TL_F64 || base > TL_BF16) return -1;
+  return base | ((p & TL_W12) ? tl::W12 : 0);
+}
+
+bool valid_prec(int p) { return fmt_code(p) >= 0; }
 
 int check_geom(tl_ctx* c, const tl_geom* g) {
   if (!g) return fail(c, TL_ERR_ARG, "geometry is NULL");
@@ -182,7 +190,7 @@ void step_coeffs(int n_steps, double sigma, double* alpha, double* beta) {
 
 struct tl_plan {
   tl_ctx* ctx = nullptr;
-  int prec = 0, n_steps = 0;
+  int prec = 0, n_steps = 0;     // prec: internal format code (tl::vprec(prec) for the vectors)
   double sigma = 0.0, alpha = 1.0, beta = 0.0;
   unsigned flags = 0;
 
@@ -278,13 +286,13 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
 int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<StepGroup>& gs) {
   if (cfg.variant != 5 && cfg.variant != 6) return 0;
   int64_t mx = 0;
-  const int R = (p->prec == TL_F64) ? 1 : p->width;
+  const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
   for (const auto& g : gs) mx = std::max(mx, tl::lds_bytes(p->prec, R, g.Lx, g.rows));
   return mx <= 160 * 1024 ? mx : -1;
 }
 
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
-  if ((cfg.variant == 5 || cfg.variant == 6) && p->prec == TL_F64 && p->width > 1)
+  if ((cfg.variant == 5 || cfg.variant == 6) && tl::vprec(p->prec) == tl::F64 && p->width > 1)
     return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernels take FP64 groups of one RHS only");
   std::vector<StepGroup> gs;
   if (make_groups(p, cfg, &gs) != TL_OK)
@@ -359,7 +367,7 @@ int plan_autotune(tl_plan* p) {
   const int cu = std::max(c->n_cu, 1);
   for (int variant : {0, 2, 3, 4, 5, 6}) {
     const bool lds_variant = variant == 5 || variant == 6;
-    if ((variant == 2 || variant == 3 || lds_variant) && p->prec == TL_F64 && p->width > 1) continue;   // would run variant 0
+    if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && p->width > 1) continue;   // would run variant 0
     if (lds_variant && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
                                  : (variant == 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
@@ -589,7 +597,7 @@ int tl_check_geom(const tl_geom* g) {
 
 size_t tl_twolinks_bytes(const tl_geom* g, int prec, int n_slices) {
   if (tl_check_geom(g) != TL_OK || !valid_prec(prec) || n_slices < 0 || n_slices > g->L[3]) return 0;
-  return (size_t)n_slices * 3 * (size_t)tl::padded_sites(vol3(*g)) * tl::kWBytes[prec];
+  return (size_t)n_slices * 3 * (size_t)tl::padded_sites(vol3(*g)) * tl::kWBytes[fmt_code(prec)];
 }
 
 int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
@@ -614,13 +622,14 @@ int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t*
   }
   TL_TRY(need_device(c));
   DeviceGuard dg(c->device);
-  if (!slices) return launch(c, "two-link build", [&] { return tl::launch_build(prec, U, g->L, 0, 0, n_slices, W, c->stream); });
+  const int code = fmt_code(prec);
+  if (!slices) return launch(c, "two-link build", [&] { return tl::launch_build(code, U, g->L, 0, 0, n_slices, W, c->stream); });
   // runs of consecutive slices share a launch
   int j = 0;
   while (j < n_slices) {
     int k = j + 1;
     while (k < n_slices && slices[k] == slices[k - 1] + 1) k++;
-    TL_TRY(launch(c, "two-link build", [&] { return tl::launch_build(prec, U, g->L, slices[j], j, k - j, W, c->stream); }));
+    TL_TRY(launch(c, "two-link build", [&] { return tl::launch_build(code, U, g->L, slices[j], j, k - j, W, c->stream); }));
     j = k;
   }
   return TL_OK;
@@ -642,13 +651,14 @@ int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_sl
   if (a < b + nat_bytes && b < a + nat_bytes) return fail(c, TL_ERR_ARG, "in and out overlap");
   TL_TRY(need_device(c));
   DeviceGuard dg(c->device);
-  const size_t fb = align256((size_t)Vp * tl::kVBytes[prec]);
+  const int code = fmt_code(prec), vp = tl::vprec(code);
+  const size_t fb = align256((size_t)Vp * tl::kVBytes[vp]);
   char* s = nullptr;
   TL_TRY(ctx_scratch(c, 1024 + 2 * fb, &s));
   StepGroup sg{};
   StepConfig cfg{0, 256, 4, 0, 0};
-  sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[prec];
-  sg.w_mu_stride = Vp * tl::kWBytes[prec];
+  sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[code];
+  sg.w_mu_stride = Vp * tl::kWBytes[code];
   sg.psi_off = 0;
   sg.rhs_stride = 0;
   sg.Lx = g->L[0];
@@ -668,10 +678,10 @@ int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_sl
   const int64_t* offdev = reinterpret_cast<const int64_t*>(s + offsetof(decltype(tab), off0));
   char* A = s + 1024;
   char* B = A + fb;
-  TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(prec, in, A, offdev, 1, V3, Vp, c->stream); }));
-  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(prec, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, -1.5, 0.25,
+  TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(vp, in, A, offdev, 1, V3, Vp, c->stream); }));
+  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(code, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, -1.5, 0.25,
                                       0, c->stream); }));
-  return launch(c, "unpack", [&] { return tl::launch_unpack(prec, B, out, offdev, 1, V3, Vp, c->stream); });
+  return launch(c, "unpack", [&] { return tl::launch_unpack(vp, B, out, offdev, 1, V3, Vp, c->stream); });
 }
 
 int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags,
@@ -705,7 +715,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
   tl_plan* p = new (std::nothrow) tl_plan();
   if (!p) return fail(c, TL_ERR_NOMEM, "host allocation failed");
   p->ctx = c;
-  p->prec = prec;
+  p->prec = fmt_code(prec);
   p->n_steps = n_steps;
   p->sigma = sigma;
   p->flags = flags;
@@ -729,7 +739,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
     std::map<int, std::vector<int>> by_slot;
     for (int r = 0; r < jc.job.n_rhs; r++)
       by_slot[slot_of(jc.job.g, jc.job.w_slices, jc.job.n_w_slices, jc.t_of_rhs[r])].push_back(r);
-    const size_t rb = align256((size_t)jc.Vp * tl::kVBytes[prec]);
+    const size_t rb = align256((size_t)jc.Vp * tl::kVBytes[p->prec]);
     for (auto& kv : by_slot) {
       const int k = (int)kv.second.size();
       const int ng = (k + max_width - 1) / max_width;
@@ -809,16 +819,17 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
   in.n_groups = (int32_t)p->groups.size();
   in.group_width = p->width;
   in.launches_per_step = (flags & TL_PLAIN) ? in.n_groups : 1;
-  double bytes = 0.0;
+  double bytes = 0.0, flops = 0.0;
   int64_t rs = 0;
   for (auto& gr : p->groups) {
     const double v3 = (double)p->jobs[gr.job].V3;
-    bytes += v3 * (3.0 * tl::kWBytes[prec] + 2.0 * gr.nr * tl::kVBytes[prec]);
+    bytes += v3 * (3.0 * tl::kWBytes[p->prec] + 2.0 * gr.nr * tl::kVBytes[p->prec]);
+    flops += v3 * (444.0 * gr.nr + (tl::is_w12(p->prec) ? 3 * 42.0 : 0.0));
     rs += (int64_t)p->jobs[gr.job].V3 * gr.nr;
   }
   in.rhs_sites = rs;
   in.bytes_per_step = bytes;
-  in.flops_per_step = 444.0 * (double)rs;
+  in.flops_per_step = flops;
   in.resident_bytes = (int64_t)(2 * p->buf_bytes + gbytes + obytes + rbytes + pbytes);
   *out = p;
   return TL_OK;
@@ -830,7 +841,7 @@ int tl_plan_load(tl_plan* p) {
   DeviceGuard dg(c->device);
   for (size_t j = 0; j < p->jobs.size(); j++) {
     const auto& jc = p->jobs[j];
-    TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(p->prec, jc.job.psi, p->buf[p->cur], p->packoff_dev + p->packoff_first[j],
+    TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(tl::vprec(p->prec), jc.job.psi, p->buf[p->cur], p->packoff_dev + p->packoff_first[j],
                                         jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
   }
   return TL_OK;
@@ -859,7 +870,7 @@ int tl_plan_store(tl_plan* p) {
   DeviceGuard dg(c->device);
   for (size_t j = 0; j < p->jobs.size(); j++) {
     const auto& jc = p->jobs[j];
-    TL_TRY(launch(c, "unpack", [&] { return tl::launch_unpack(p->prec, p->buf[p->cur], jc.job.psi, p->packoff_dev + p->packoff_first[j],
+    TL_TRY(launch(c, "unpack", [&] { return tl::launch_unpack(tl::vprec(p->prec), p->buf[p->cur], jc.job.psi, p->packoff_dev + p->packoff_first[j],
                                           jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
   }
   return TL_OK;
@@ -873,7 +884,7 @@ int tl_plan_reduce(tl_plan* p, int kind, const tl_plan* other, double* out) {
   const char* b = nullptr;
   if (kind == TL_DOT) {
     if (!other) return fail(c, TL_ERR_ARG, "TL_DOT needs a second plan");
-    if (other->ctx != c || other->prec != p->prec || other->buf_bytes != p->buf_bytes || other->res.size() != p->res.size())
+    if (other->ctx != c || tl::vprec(other->prec) != tl::vprec(p->prec) || other->buf_bytes != p->buf_bytes || other->res.size() != p->res.size())
       return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in context, precision or shape");
     for (size_t i = 0; i < p->res.size(); i++)
       if (other->res[i].off != p->res[i].off) return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in layout");
@@ -881,7 +892,7 @@ int tl_plan_reduce(tl_plan* p, int kind, const tl_plan* other, double* out) {
   }
   DeviceGuard dg(c->device);
   // a (this) is the second argument of <other, this>
-  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, p->prec, p->buf[p->cur], b, p->red_dev, (int)p->res.size(), p->max_v3,
+  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, tl::vprec(p->prec), p->buf[p->cur], b, p->red_dev, (int)p->res.size(), p->max_v3,
                                         p->partials, out, c->stream); });
 }
 

@@ -1,0 +1,1103 @@
+// Smearing step kernels (eq. tlSmear with eq. tlLapl1) for gfx950, per right-hand side r:
+//   out_r(x) = alpha in_r(x) + beta sum_mu [W_mu(x) in_r(x+2mu^) + W_mu^dag(x-2mu^) in_r(x-2mu^)]
+// with alpha = 1 - 6 sigma/(4n) and beta = sigma/(4n), which is
+// in + (sigma/n) Lap in.  (alpha = -3/2, beta = 1/4 gives Lap itself.)
+// The RHS of one group live on the same slice and share every two-link load.
+// Accumulation order per site is fixed (x fwd, x bwd, y fwd, y bwd, z fwd,
+// z bwd, then the axpy), written with explicit fused multiply-adds, so every
+// kernel variant and tiling produces bit-identical results.
+//
+// Included by one translation unit per storage precision (tl_step_<prec>.hip),
+// each instantiating both two-link forms of its precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "tl_format.h"
+#include "tl_internal.h"
+
+namespace tl {
+
+namespace {
+
+constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b % 8).  Give the workgroups of one XCD a contiguous range of the work
+// list and let them sweep it together, so neighbouring tiles (which share
+// halo sites and two-links) meet in the same L2.  Correctness does not
+// depend on the dispatch order.
+struct TileSweep {
+  int first, stride, end;
+};
+
+__device__ __forceinline__ TileSweep xcd_sweep(int n_tiles) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int k = b % kXcds, j = b / kXcds;
+  const int q = G / kXcds, r = G % kXcds;
+  const int cnt = q + (k < r ? 1 : 0);                     // workgroups on this XCD
+  const int ord0 = k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q;  // their first ordinal
+  const int t0 = (int)(((int64_t)n_tiles * ord0) / G);
+  const int t1 = (int)(((int64_t)n_tiles * (ord0 + cnt)) / G);
+  return {t0 + j, cnt, t1};
+}
+
+// v mod L for v in [-2L, 3L), branch-free
+__device__ __forceinline__ int wrap_sel(int v, int L) {
+  v = v >= L ? v - L : v;
+  v = v >= L ? v - L : v;
+  v = v < 0 ? v + L : v;
+  v = v < 0 ? v + L : v;
+  return v;
+}
+
+__device__ __forceinline__ int wrap_step(int v, int d, int L) {
+  v += d;
+  while (v >= L) v -= L;
+  while (v < 0) v += L;
+  return v;
+}
+
+// acc += M v   (3x3 complex times colour vector)
+template <typename T>
+__device__ __forceinline__ void mv_acc(const T (&m)[18], const T (&v)[6], T (&acc)[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    T re = acc[2 * a], im = acc[2 * a + 1];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const T mr = m[2 * (3 * a + b)], mi = m[2 * (3 * a + b) + 1];
+      re = fma_(mr, v[2 * b], re);
+      re = fma_(-mi, v[2 * b + 1], re);
+      im = fma_(mr, v[2 * b + 1], im);
+      im = fma_(mi, v[2 * b], im);
+    }
+    acc[2 * a] = re;
+    acc[2 * a + 1] = im;
+  }
+}
+
+// acc += M^dag v
+template <typename T>
+__device__ __forceinline__ void mdv_acc(const T (&m)[18], const T (&v)[6], T (&acc)[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    T re = acc[2 * a], im = acc[2 * a + 1];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const T mr = m[2 * (3 * b + a)], mi = m[2 * (3 * b + a) + 1];
+      re = fma_(mr, v[2 * b], re);
+      re = fma_(mi, v[2 * b + 1], re);
+      im = fma_(mr, v[2 * b + 1], im);
+      im = fma_(-mi, v[2 * b], im);
+    }
+    acc[2 * a] = re;
+    acc[2 * a + 1] = im;
+  }
+}
+
+__device__ __forceinline__ int find_group(const StepGroup* __restrict__ groups, int n_groups, int tile) {
+  int lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ step kernels
+
+// Variant 0: each thread owns one (x, y) site of the tile and walks the tile's
+// z planes; every neighbour value comes through L1/L2.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  constexpr int VB = kVBytes[P];
+  (void)VB;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};    // +2 in x, y
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};  // -2 in x, y
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t zp = (int64_t)wrap_step(z, 2, Lz) * LxLy;
+      const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t fwd[3] = {zo + xyp[0], zo + xyp[1], zp + xy};
+      const int64_t bwd[3] = {zo + xym[0], zo + xym[1], zm + xy};
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 3; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, fwd[mu], v);
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wmu[mu], Vp, bwd[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, bwd[mu], v);
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real v[6], o[6];
+        F::load_v(pin[r], Vp, site, v);
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+    }
+  }
+}
+
+// Variant 1: as variant 0, but each thread keeps the colour vectors of planes
+// z-2 .. z+2 in a register ring while it marches up the tile's z range, so the
+// z hops and the centre term read no memory; one new plane is loaded per step.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    real ring[5][R][6];   // planes z-2, z-1, z, z+1, z+2
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(z0, k - 2, Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        F::load_v(pin[r], Vp, zo, ring[k][r]);
+    }
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t zp = (int64_t)wrap_step(z, 2, Lz) * LxLy + xy;
+      const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        F::load_v(pin[r], Vp, zp, ring[4][r]);
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xyp[mu], v);
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xym[mu], v);
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+      {
+        real m[18];
+        F::load_w(Wmu[2], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mv_acc(m, ring[4][r], acc[r]);
+        F::load_w(Wmu[2], Vp, zm, m);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mdv_acc(m, ring[0][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+    }
+  }
+}
+
+// Variant 2: z-marching with register rings for both the colour vectors of
+// planes z-2 .. z+2 and the z two-links of planes z-2 .. z, so every z hop
+// and the centre term read no memory and each W_z is loaded once.  Even
+// z chunks march up and odd chunks march down: two neighbouring chunks reach
+// the planes they share at the same time, so those halo planes are still in
+// L2 for the second reader.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ groups, int n_groups,
+                                                  int tile_base, int n_tiles, int tz,
+                                                  const char* __restrict__ in, char* __restrict__ out,
+                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
+    // is unconditional, so the compiler can keep many loads in flight.
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;       // first plane of the march
+    // ring[k] holds plane zs + dz*(k-2) relative to the current plane, i.e. k = 2 is
+    // the current plane and k = 4 the one two planes ahead in the march direction.
+    real ring[5][R][6];
+    // Each step loads one new W_z into wz[2]: W_z(z) marching up, W_z(z-2) marching
+    // down; wz[k] was loaded 2-k steps earlier.  So wz[k] = W_z(z-2+k) marching up
+    // and W_z(z-k) marching down: both hops' two-links are wz[0] and wz[2].
+    real wz[3][18];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        F::load_v(pin[r], Vp, zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
+      F::load_w(Wmu[2], Vp, zo, wz[k]);
+    }
+    for (int i = 0; i < nz; i++) {
+      const int z = zs + dz * i;
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      {
+        const int64_t za = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy + xy;   // two planes ahead
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          F::load_v(pin[r], Vp, za, ring[4][r]);
+        // marching up the new W_z is the current plane's (forward hop); marching down it is the
+        // plane two below (backward hop)
+        const int64_t zw = up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+        F::load_w(Wmu[2], Vp, zw, wz[2]);
+      }
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        real m[18];
+        F::load_w(Wmu[mu], Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xyp[mu], v);
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, zo + xym[mu], v);
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+      // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mv_acc(wz[2], ring[4][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mdv_acc(wz[0], ring[0][r], acc[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mv_acc(wz[0], ring[0][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+          mdv_acc(wz[2], ring[4][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+    }
+  }
+}
+
+// In-plane hops (x forward, x backward, y forward, y backward, in that order)
+// of the site xy of plane zo, for every RHS slot.
+template <class F, int R, typename real>
+__device__ __forceinline__ void inplane_hops(const char* const (&Wmu)[3], const char* const (&pin)[R], int64_t Vp,
+                                             int64_t zo, int xy, const int (&xyp)[2], const int (&xym)[2],
+                                             real (&acc)[R][6]) {
+#pragma unroll
+  for (int r = 0; r < R; r++)
+#pragma unroll
+    for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+  for (int mu = 0; mu < 2; mu++) {
+    real m[18];
+    F::load_w(Wmu[mu], Vp, zo + xy, m);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      real v[6];
+      F::load_v(pin[r], Vp, zo + xyp[mu], v);
+      mv_acc(m, v, acc[r]);
+    }
+    F::load_w(Wmu[mu], Vp, zo + xym[mu], m);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      real v[6];
+      F::load_v(pin[r], Vp, zo + xym[mu], v);
+      mdv_acc(m, v, acc[r]);
+    }
+  }
+}
+
+// Variant 3: z-marching in which every plane is read from memory once, at
+// the front of the march.  When plane f = z+2 is first touched, the thread
+// loads its own colour vectors there (register ring of planes z-2 .. z+2)
+// and also computes the in-plane hops of plane f, whose neighbour rows the
+// workgroup and its y-neighbour workgroups are loading in the same step, so
+// they come from L2.  Those partial sums wait in a ring for two steps; at
+// plane z the two z hops (W_z from a register ring) and the axpy complete
+// the site.  Chunks alternate their march direction as in variant 2.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};
+    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};
+    const char* const Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
+    const int nr = g.nr;
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;
+    real ring[5][R][6];      // own colour vectors, planes z-2dz .. z+2dz
+    real part[2][R][6];      // in-plane partial sums of planes z and z+dz
+    real wz[3][18];          // as in variant 2: wz[0], wz[2] are the two z hops' links
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int64_t zo = (int64_t)wrap_step(zs, dz * (k - 2), Lz) * LxLy + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int64_t zw = (int64_t)wrap_step(zs, up ? k - 2 : -k, Lz) * LxLy + xy;
+      F::load_w(Wmu[2], Vp, zw, wz[k]);
+      const int64_t zp = (int64_t)wrap_step(zs, dz * k, Lz) * LxLy;
+      if (k < nz) inplane_hops<F, R>(Wmu, pin, Vp, zp, xy, xyp, xym, part[k]);
+    }
+    for (int i = 0; i < nz; i++) {
+      const int z = zs + dz * i;
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t site = zo + xy;
+      const int64_t zf = (int64_t)wrap_step(z, 2 * dz, Lz) * LxLy;   // front plane
+#pragma unroll
+      for (int r = 0; r < R; r++) F::load_v(pin[r], Vp, zf + xy, ring[4][r]);
+      F::load_w(Wmu[2], Vp, up ? site : (int64_t)wrap_step(z, -2, Lz) * LxLy + xy, wz[2]);
+      real front[R][6];
+      if (i + 2 < nz) inplane_hops<F, R>(Wmu, pin, Vp, zf, xy, xyp, xym, front);
+      // complete plane z: in-plane part, then z forward, then z backward, then the axpy
+      const real (&fw)[18] = up ? wz[2] : wz[0];
+      const real (&bw)[18] = up ? wz[0] : wz[2];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        mv_acc(fw, up ? ring[4][r] : ring[0][r], part[0][r]);
+        mdv_acc(bw, up ? ring[0][r] : ring[4][r], part[0][r]);
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, part[0][r][c], alpha * ring[2][r][c]);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+          part[0][r][c] = part[1][r][c];
+          part[1][r][c] = front[r][c];
+        }
+    }
+  }
+}
+
+// Variant 4: as variant 0, but the loop over directions stays rolled, so only
+// one direction's loads (two two-links and 2R colour vectors) are live at a
+// time.  Fewer registers allow more waves per SIMD, which hide the memory
+// latency of each direction and overlap one wave's arithmetic with the
+// others' loads.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using F = Fmt<P>;
+  using real = typename F::real;
+  const TileSweep sw = xcd_sweep(n_tiles);
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int txy = local - tzi * g.n_xy_tiles;
+    const int LxLy = Lx * Ly;
+    const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
+    if (xy >= LxLy) continue;
+    const int y = xy / Lx, x = xy - y * Lx;
+    const int xf = y * Lx + wrap_step(x, 2, Lx), xb = y * Lx + wrap_step(x, -2, Lx);
+    const int yf = wrap_step(y, 2, Ly) * Lx + x, yb = wrap_step(y, -2, Ly) * Lx + x;
+    const int nr = g.nr;
+    const char* pin[R];
+    char* pout[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      pin[r] = in + o;
+      pout[r] = out + o;
+    }
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, Lz);
+    for (int z = z0; z < z1; z++) {
+      const int64_t zo = (int64_t)z * LxLy;
+      const int64_t zf = (int64_t)wrap_step(z, 2, Lz) * LxLy + xy;
+      const int64_t zb = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+      const int64_t site = zo + xy;
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll 1
+      for (int mu = 0; mu < 3; mu++) {
+        const char* Wm = g.W + mu * g.w_mu_stride;
+        const int64_t f = mu == 0 ? zo + xf : (mu == 1 ? zo + yf : zf);
+        const int64_t b = mu == 0 ? zo + xb : (mu == 1 ? zo + yb : zb);
+        real m[18];
+        F::load_w(Wm, Vp, site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, f, v);
+          mv_acc(m, v, acc[r]);
+        }
+        F::load_w(Wm, Vp, b, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+          F::load_v(pin[r], Vp, b, v);
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real v[6], o[6];
+        F::load_v(pin[r], Vp, site, v);
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
+        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+      }
+    }
+  }
+}
+
+template <typename T> struct Complex2;
+template <> struct Complex2<float> { using type = float2; };
+template <> struct Complex2<double> { using type = double2; };
+
+// Variant 5: z-marching as variant 2 (register rings of colour vectors and z
+// two-links, alternating chunk directions) on tiles of `rows` full rows of the
+// xy plane.  Each step every thread publishes its current-plane colour vectors
+// to LDS and the first 4*Lx threads load the four halo rows (two above, two
+// below, periodic); all in-plane neighbours are then read from LDS.  Two LDS
+// buffers alternate by step, so one barrier per step suffices.  Threads past
+// the tile's rows only help with the barrier and the halo.  Fields are
+// addressed through per-plane base pointers set up once per tile and 32-bit
+// site offsets; plane wraps are branch-free.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ groups, int n_groups,
+                                                 int tile_base, int n_tiles, int tz,
+                                                 const char* __restrict__ in, char* __restrict__ out,
+                                                 typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
+  using c2 = typename Complex2<real>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  c2* const lds = reinterpret_cast<c2*>(lds_raw);
+  const TileSweep sw = xcd_sweep(n_tiles);
+  int it = 0;   // steps done by this workgroup: selects the LDS buffer across tiles
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;
+    const int y0 = (local - tzi * g.n_xy_tiles) * rows;
+    const int LxLy = Lx * Ly;
+    const int t = (int)threadIdx.x;
+    const int trow = t / Lx, x = t - trow * Lx;
+    const bool active = trow < rows;
+    const int row = active ? trow : 0;
+    const int y = y0 + row;
+    const int xy = y * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - 2, Lx);
+    const int ybw = wrap_sel(y - 2, Ly) * Lx + x;
+    const int nsite = (rows + 4) * Lx;
+    const int own = (row + 2) * Lx + x;
+    const int sxf = (row + 2) * Lx + wrap_sel(x + 2, Lx), sxb = (row + 2) * Lx + wrap_sel(x - 2, Lx);
+    const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
+    const bool halo = t < 4 * Lx;
+    const int hr = halo ? trow : 0;
+    const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;          // halo row relative to y0
+    const int hxy = wrap_sel(y0 + hrho, Ly) * Lx + x;
+    const int hslot = (hrho + 2) * Lx + x;
+    const char* wp[3][PL::NW];
+#pragma unroll
+    for (int mu = 0; mu < 3; mu++) PL::w(g.W + mu * g.w_mu_stride, Vp, wp[mu]);
+    const int nr = g.nr;
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
+    }
+    const int zlo = tzi * tz;
+    const int nz = min(zlo + tz, Lz) - zlo;
+    const bool up = (tzi & 1) == 0;
+    const int dz = up ? 1 : -1;
+    const int zs = up ? zlo : zlo + nz - 1;
+    real ring[5][R][6];
+    real wz[3][18];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t zo = (uint32_t)(wrap_sel(zs + dz * (k - 2), Lz) * LxLy + xy);
+#pragma unroll
+      for (int r = 0; r < R; r++) PL::load_v(ip[r], zo, ring[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++)
+      PL::load_w(wp[2], (uint32_t)(wrap_sel(zs + (up ? k - 2 : -k), Lz) * LxLy + xy), wz[k]);
+    for (int i = 0; i < nz; i++, it++) {
+      const int z = zs + dz * i;
+      const uint32_t zo = (uint32_t)(z * LxLy);
+      const uint32_t site = zo + xy;
+      {
+        const uint32_t za = (uint32_t)(wrap_sel(z + 2 * dz, Lz) * LxLy + xy);
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], za, ring[4][r]);
+        const uint32_t zw = up ? site : (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy);
+        PL::load_w(wp[2], zw, wz[2]);
+      }
+      c2* const buf = lds + (it & 1) * (R * 3) * nsite;
+      if (halo) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real hv[6];
+          PL::load_v(ip[r], zo + hxy, hv);
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[2 * c], hv[2 * c + 1]};
+        }
+      }
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[2][r][2 * c], ring[2][r][2 * c + 1]};
+      }
+      __syncthreads();
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+#pragma unroll
+      for (int mu = 0; mu < 2; mu++) {
+        const int sf = mu == 0 ? sxf : syf, sb = mu == 0 ? sxb : syb;
+        real m[18];
+        PL::load_w(wp[mu], site, m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const c2 w = buf[(r * 3 + c) * nsite + sf];
+            v[2 * c] = w.x;
+            v[2 * c + 1] = w.y;
+          }
+          mv_acc(m, v, acc[r]);
+        }
+        PL::load_w(wp[mu], zo + (uint32_t)(mu == 0 ? xbw : ybw), m);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real v[6];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const c2 w = buf[(r * 3 + c) * nsite + sb];
+            v[2 * c] = w.x;
+            v[2 * c + 1] = w.y;
+          }
+          mdv_acc(m, v, acc[r]);
+        }
+      }
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++) mv_acc(wz[2], ring[4][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++) mdv_acc(wz[0], ring[0][r], acc[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) mv_acc(wz[0], ring[0][r], acc[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++) mdv_acc(wz[2], ring[4][r], acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[2][r][c]);
+        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) ring[k][r][c] = ring[k + 1][r][c];
+#pragma unroll
+      for (int c = 0; c < 18; c++) {
+        wz[0][c] = wz[1][c];
+        wz[1][c] = wz[2][c];
+      }
+    }
+  }
+}
+
+// Variant 6: as variant 5, but each tile marches a chain of planes z, z+2,
+// z+4, ... (mod Lz; two chains when Lz is even, one when odd), so the z hops
+// are the chain neighbours: a ring of three colour-vector planes and two z
+// two-links suffices.  The registers this frees hold the four in-plane
+// two-links, which are loaded before the LDS barrier so their latency
+// overlaps it.  Tiles: (row tile, chain, chunk of tz chain positions); chunks
+// alternate their march direction along the chain.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__ groups, int n_groups,
+                                                   int tile_base, int n_tiles, int tz,
+                                                   const char* __restrict__ in, char* __restrict__ out,
+                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
+  using c2 = typename Complex2<real>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  c2* const lds = reinterpret_cast<c2*>(lds_raw);
+  const TileSweep sw = xcd_sweep(n_tiles);
+  int it = 0;
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;          // chain chunk index: n_z_tiles = chains * chunks
+    const int y0 = (local - tzi * g.n_xy_tiles) * rows;
+    const int chains = (Lz & 1) ? 1 : 2;
+    const int clen = Lz / chains;                  // planes per chain
+    const int chunks = (clen + tz - 1) / tz;
+    const int chain = tzi / chunks, chunk = tzi - chain * chunks;
+    const int LxLy = Lx * Ly;
+    const int t = (int)threadIdx.x;
+    const int trow = t / Lx, x = t - trow * Lx;
+    const bool active = trow < rows;
+    const int row = active ? trow : 0;
+    const int y = y0 + row;
+    const int xy = y * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - 2, Lx);
+    const int ybw = wrap_sel(y - 2, Ly) * Lx + x;
+    const int nsite = (rows + 4) * Lx;
+    const int own = (row + 2) * Lx + x;
+    const int sxf = (row + 2) * Lx + wrap_sel(x + 2, Lx), sxb = (row + 2) * Lx + wrap_sel(x - 2, Lx);
+    const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
+    const bool halo = t < 4 * Lx;
+    const int hr = halo ? trow : 0;
+    const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;
+    const int hxy = wrap_sel(y0 + hrho, Ly) * Lx + x;
+    const int hslot = (hrho + 2) * Lx + x;
+    const char* wp[3][PL::NW];
+#pragma unroll
+    for (int mu = 0; mu < 3; mu++) PL::w(g.W + mu * g.w_mu_stride, Vp, wp[mu]);
+    const int nr = g.nr;
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
+    }
+    const int k0 = chunk * tz;
+    const int nz = min(k0 + tz, clen) - k0;        // planes of this chunk
+    const bool up = (chunk & 1) == 0;
+    // first plane of the march: chain position k0 (up) or k0 + nz - 1 (down)
+    const int kf = up ? k0 : k0 + nz - 1;
+    int z = wrap_sel(chain + 2 * kf, Lz);          // kf < Lz, so the argument is below 3 Lz
+    const int step = up ? 2 : -2;                  // plane step along the march
+    // ring[0]: plane behind in the march, ring[1]: current, ring[2]: ahead (loaded each step)
+    real ring[3][R][6];
+    real wz[2][18];   // wz[0] loaded one step earlier, wz[1] this step
+    {
+      const uint32_t zb = (uint32_t)(wrap_sel(z - step, Lz) * LxLy + xy);
+      const uint32_t zc = (uint32_t)(z * LxLy + xy);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        PL::load_v(ip[r], zb, ring[0][r]);
+        PL::load_v(ip[r], zc, ring[1][r]);
+      }
+      // marching up the link loaded at plane z is W_z(z); marching down it is W_z(z-2),
+      // so before the first step wz[0] holds W_z(z-2) (up) or W_z(z) (down)
+      PL::load_w(wp[2], up ? (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy) : zc, wz[0]);
+    }
+    for (int i = 0; i < nz; i++, it++) {
+      const uint32_t zo = (uint32_t)(z * LxLy);
+      const uint32_t site = zo + xy;
+      const int za = wrap_sel(z + step, Lz);
+#pragma unroll
+      for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ring[2][r]);
+      PL::load_w_raw(wp[2], up ? site : (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy), wz[1]);
+      real mxf[18], mxb[18], myf[18], myb[18];
+      PL::load_w_raw(wp[0], site, mxf);
+      PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
+      PL::load_w_raw(wp[1], site, myf);
+      PL::load_w_raw(wp[1], zo + (uint32_t)ybw, myb);
+      c2* const buf = lds + (it & 1) * (R * 3) * nsite;
+      if (halo) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          real hv[6];
+          PL::load_v(ip[r], zo + hxy, hv);
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[2 * c], hv[2 * c + 1]};
+        }
+      }
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[1][r][2 * c], ring[1][r][2 * c + 1]};
+      }
+      __syncthreads();
+      PL::finish_w(wz[1]);
+      PL::finish_w(mxf);
+      PL::finish_w(mxb);
+      PL::finish_w(myf);
+      PL::finish_w(myb);
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+        real v[6];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + sxf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(mxf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + sxb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(mxb, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(myf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(myb, v, acc[r]);
+      }
+      // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          mv_acc(wz[1], ring[2][r], acc[r]);
+          mdv_acc(wz[0], ring[0][r], acc[r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          mv_acc(wz[0], ring[0][r], acc[r]);
+          mdv_acc(wz[1], ring[2][r], acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[1][r][c]);
+        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+          ring[0][r][c] = ring[1][r][c];
+          ring[1][r][c] = ring[2][r][c];
+        }
+#pragma unroll
+      for (int c = 0; c < 18; c++) wz[0][c] = wz[1][c];
+      z = za;
+    }
+  }
+}
+
+constexpr int kMaxLds = 160 * 1024;   // LDS per compute unit on gfx950
+
+template <int P, int R, bool NT>
+hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
+  using real = typename Fmt<P>::real;
+  const int grid = cfg.grid > 0 ? std::min(cfg.grid, n_tiles) : n_tiles;
+  // The ring kernels are instantiated only where their registers fit; FP64 with wider
+  // groups runs the direct kernel, which computes the same bits.
+  // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
+  // never selects it for FP64 groups wider than one RHS)
+  if ((cfg.variant == 5 || cfg.variant == 6) && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
+  const bool direct = cfg.variant == 0 || (vprec(P) == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
+                                           cfg.variant != 5 && cfg.variant != 6);
+  (void)lds;
+  constexpr int R1 = (vprec(P) == F64 && R > 2) ? 1 : R;
+  constexpr int R2 = (vprec(P) == F64) ? 1 : R;
+  const real a = (real)alpha, b = (real)beta;
+  if (direct)
+    step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 1)
+    step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 2)
+    step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 3)
+    step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 4)
+    step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+  else if (cfg.variant == 6) {
+    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+    step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                               a, b);
+  } else if (cfg.variant == 5) {
+    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+    step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                             a, b);
+  } else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int P, int R>
+hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
+  if (cfg.nt)
+    return launch_step_n<P, R, true>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+  return launch_step_n<P, R, false>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+}
+
+template <int P, int R>
+hipError_t allow_lds() {
+  for (const void* f : {reinterpret_cast<const void*>(&step_zlds<P, R, false>),
+                        reinterpret_cast<const void*>(&step_zlds<P, R, true>),
+                        reinterpret_cast<const void*>(&step_zchain<P, R, false>),
+                        reinterpret_cast<const void*>(&step_zchain<P, R, true>)}) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int P>
+hipError_t launch_step_p(int width, const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
+                         int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
+                         hipStream_t s) {
+  switch (width) {
+    case 1: return launch_step_t<P, 1>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 2: return launch_step_t<P, 2>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 3: return launch_step_t<P, 3>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case 4: return launch_step_t<P, 4>(cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Both two-link forms of storage precision P.
+template <int P>
+hipError_t launch_step_both(bool w12, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
+                            int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
+                            int64_t lds, hipStream_t s) {
+  if (w12)
+    return launch_step_p<P | W12>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+  return launch_step_p<P>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+}
+
+template <int P>
+hipError_t step_attributes_both() {
+  hipError_t e = hipSuccess;
+  if constexpr (P == F64) {
+    for (hipError_t r : {allow_lds<P, 1>(), allow_lds<P | W12, 1>()})
+      if (r != hipSuccess) e = r;
+  } else {
+    for (hipError_t r : {allow_lds<P, 1>(), allow_lds<P, 2>(), allow_lds<P, 3>(), allow_lds<P, 4>(),
+                         allow_lds<P | W12, 1>(), allow_lds<P | W12, 2>(), allow_lds<P | W12, 3>(),
+                         allow_lds<P | W12, 4>()})
+      if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
+}  // namespace
+
+}  // namespace tl

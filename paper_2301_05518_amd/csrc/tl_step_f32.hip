@@ -1,0 +1,15 @@
+// Smearing step kernels stored in F32: both two-link forms (18 and 12 reals).
+#include "tl_step.h"
+
+namespace tl {
+
+hipError_t launch_step_f32(bool w12, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
+                          int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
+                          int64_t lds, hipStream_t stream) {
+  return launch_step_both<F32>(w12, width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds,
+                          stream);
+}
+
+hipError_t step_attributes_f32() { return step_attributes_both<F32>(); }
+
+}  // namespace tl

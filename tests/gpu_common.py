@@ -21,15 +21,29 @@ from oracle import checks
 #   four-fold cancellation between -6 psi and the hops) pins those tightly.
 UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16s": 2.0 ** -11, "bf16": 2.0 ** -8}
 
+# Twelve-real two-links ("<prec>-w12"): the rebuilt third row inherits the
+# rounding of the two stored unit rows (about u each through the cross
+# product) plus four rounded operations per entry, up to about 4u, so the
+# two-link term of the per-step budget grows from u to about 4u: 2 u per
+# step becomes 5 u (n-step bound 5 (n + 1) u), and the Laplacian bound grows
+# by the same factor 2.5.  FP64 keeps its 1e-12 target.
+W12_FACTOR = 2.5
+
+
+def _split(prec: str):
+    return (prec[:-4], True) if prec.endswith("-w12") else (prec, False)
+
 
 def tol(prec: str, n: int) -> float:
-    if prec == "f64":
+    base, w12 = _split(prec)
+    if base == "f64":
         return 1e-12
-    return 2.0 * (n + 1) * UNIT_ROUNDOFF[prec]
+    return 2.0 * (n + 1) * UNIT_ROUNDOFF[base] * (W12_FACTOR if w12 else 1.0)
 
 
 def tol_lap(prec: str) -> float:
-    return 1e-14 if prec == "f64" else 16.0 * UNIT_ROUNDOFF[prec]
+    base, w12 = _split(prec)
+    return 1e-14 if base == "f64" else 16.0 * UNIT_ROUNDOFF[base] * (W12_FACTOR if w12 else 1.0)
 
 
 def log(msg: str):

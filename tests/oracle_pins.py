@@ -61,6 +61,19 @@ def pin_twolinks_su3(orc):
     assert np.abs(np.linalg.det(W) - 1.0).max() < TOL
 
 
+def pin_twolinks_third_row(orc):
+    """A product of SU(3) links has third row conj(row0 x row1), the identity behind the
+    twelve-real two-link storage; links scaled off SU(3) break it (so the storage is valid
+    for special unitary links only)."""
+    U = _haar_links((5, 4, 3, 2), 14)
+    W = orc.build_twolinks(U)
+    rebuilt = np.conj(np.cross(W[..., 0, :], W[..., 1, :]))
+    assert np.abs(rebuilt - W[..., 2, :]).max() < TOL
+    Ws = orc.build_twolinks(1.1 * U)
+    rebuilt = np.conj(np.cross(Ws[..., 0, :], Ws[..., 1, :]))
+    assert np.abs(rebuilt - Ws[..., 2, :]).max() > 0.1
+
+
 def pin_twolinks_covariance(orc):
     """Gauge covariance: U -> G U G^dag(x+mu^) gives W -> G(x) W G^dag(x+2mu^).
 

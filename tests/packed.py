@@ -10,7 +10,8 @@ from __future__ import annotations
 
 import numpy as np
 
-W_BYTES = {"f64": 144, "f32": 72, "f16s": 40, "bf16": 36}
+W_BYTES = {"f64": 144, "f32": 72, "f16s": 40, "bf16": 36,
+           "f64-w12": 96, "f32-w12": 48, "f16s-w12": 24, "bf16-w12": 24}
 V_BYTES = {"f64": 48, "f32": 24, "f16s": 16, "bf16": 12}
 
 
@@ -23,7 +24,9 @@ def _bf16_to_f32(u16: np.ndarray) -> np.ndarray:
 
 
 def decode_twolinks(raw: np.ndarray, L, prec: str, n_slots: int) -> np.ndarray:
-    """Packed two-link bytes -> complex128 [slot][Lz][Ly][Lx][mu][3][3]."""
+    """Packed two-link bytes -> complex128 [slot][Lz][Ly][Lx][mu][3][3].
+
+    Twelve-real forms ("<prec>-w12") hold rows 0 and 1 only; row 2 comes back as NaN."""
     Lx, Ly, Lz = L[:3]
     v3 = Lx * Ly * Lz
     vp = padded(v3)
@@ -44,6 +47,21 @@ def decode_twolinks(raw: np.ndarray, L, prec: str, n_slots: int) -> np.ndarray:
                 p8 = blk[: 32 * vp].view(np.uint16).reshape(2, vp, 8)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 16)
                 p2 = blk[32 * vp: 36 * vp].view(np.uint16).reshape(vp, 2)[:v3]
                 reals[s, mu] = _bf16_to_f32(np.concatenate([p8, p2], axis=1))
+            elif prec.endswith("-w12"):
+                base = prec[:-4]
+                reals[s, mu, :, 12:] = np.nan
+                if base == "f64":
+                    reals[s, mu, :, :12] = blk.view(np.float64).reshape(6, vp, 2)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 12)
+                elif base == "f32":
+                    reals[s, mu, :, :12] = blk.view(np.float32).reshape(3, vp, 4)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 12)
+                else:
+                    p8 = blk[: 16 * vp].view(np.uint16).reshape(vp, 8)[:v3]
+                    p4 = blk[16 * vp: 24 * vp].view(np.uint16).reshape(vp, 4)[:v3]
+                    bits = np.concatenate([p8, p4], axis=1)
+                    if base == "bf16":
+                        reals[s, mu, :, :12] = _bf16_to_f32(bits)
+                    else:
+                        reals[s, mu, :, :12] = bits.view(np.float16).astype(np.float64)
             elif prec == "f16s":
                 p8 = blk[: 32 * vp].view(np.float16).reshape(2, vp, 8)[:, :v3, :].transpose(1, 0, 2).reshape(v3, 16)
                 tail = blk[32 * vp: 40 * vp].reshape(vp, 8)[:v3]

@@ -62,6 +62,11 @@ def test_twolinks_bytes(lib):
     assert lib.tl_twolinks_bytes(ctypes.byref(g), 7, 1) == 0
     assert lib.tl_twolinks_bytes(ctypes.byref(g), 1, 3) == 0
     assert lib.tl_twolinks_bytes(ctypes.byref(geom(0, 4, 4, 4)), 1, 1) == 0
+    # twelve-real forms: two rows of 3 complex per matrix
+    for p, b in {0: 96, 1: 48, 2: 24, 3: 24}.items():
+        assert lib.tl_twolinks_bytes(ctypes.byref(geom(8, 8, 8, 4)), p | _lib.TL_W12, 2) == 2 * 3 * 512 * b
+    for bad in (4, 7 | _lib.TL_W12, 32, -1, _lib.TL_W12 | 8):
+        assert lib.tl_twolinks_bytes(ctypes.byref(geom(8, 8, 8, 4)), bad, 1) == 0
 
 
 def test_check_geom(lib):

@@ -98,6 +98,12 @@ def test_workload3_64cube_24rhs(ctx, torch):
     assert worst < tol("f32", n)
 
 
+def test_workload3_w12(ctx, torch):
+    """Workload 3 with twelve-real two-links (FP32 rows, third row rebuilt): 3 RHS sampled."""
+    worst, n = run_workload(ctx, torch, 3, "f32-w12", 6, lambda k: [0, 11, k - 1])
+    assert worst < tol("f32-w12", n)
+
+
 def test_workload4_uneven_bf16(ctx, torch):
     """Uneven batch 24^3x48 + 32^3x64 + 48^3x96, Z2 sources, N=40, BF16: first and last RHS of each lattice."""
     worst, n = run_workload(ctx, torch, 4, "bf16", 6, lambda k: sorted({0, k - 1}))
