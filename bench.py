@@ -250,7 +250,8 @@ def main():
     traffic = measured_traffic(key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain"][info["variant"]],
+                "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
+                           "step_zpipe"][info["variant"]],
                 "algorithmic_bytes_per_launch": info["bytes_per_step"],
                 "avg_launch_ms": round(step_ms, 5), "copy_GBs": round(copy_gbs, 1)}
     log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")

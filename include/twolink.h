@@ -115,7 +115,7 @@ typedef struct {
     int32_t n_groups;          /* RHS groups: RHS of one slice that share each W load */
     int32_t group_width;       /* largest group */
     int32_t n_tiles;           /* work-list entries per step */
-    int32_t variant;           /* step kernel variant (0 direct, 1-3 z-marching, 4 rolled) */
+    int32_t variant;           /* step kernel variant (0 direct, 1-3 z-marching, 4 rolled, 5-7 LDS row tiles) */
     int32_t block;             /* threads per workgroup */
     int32_t tz;                /* z planes per tile */
     int32_t grid;              /* workgroups per step launch */

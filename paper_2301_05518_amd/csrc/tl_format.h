@@ -98,6 +98,16 @@ __device__ __forceinline__ void su3_row3(T (&m)[18]) {
   }
 }
 
+// Load a word of a packed field through a global-address-space pointer.  The
+// field pointers come from work-list entries in memory, whose address space
+// the compiler cannot infer: plain dereferences would compile to flat loads,
+// which also count against the LDS wait counter, so that every wait for LDS
+// data (at a barrier) would wait for these loads too.
+template <typename V>
+__device__ __forceinline__ V ldg(const char* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+
 template <int P> struct Fmt;
 
 // ------------------------------------------------------------------ FP64
@@ -105,10 +115,9 @@ template <> struct Fmt<F64> {
   using real = double;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    const double2* p = reinterpret_cast<const double2*>(b);
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-      double2 v = p[k * Vp + i];
+      const v2d v = ldg<v2d>(b + (k * Vp + i) * 16);
       m[2 * k] = (T)v.x;
       m[2 * k + 1] = (T)v.y;
     }
@@ -120,10 +129,9 @@ template <> struct Fmt<F64> {
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
-    const double2* p = reinterpret_cast<const double2*>(b);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      double2 w = p[c * Vp + i];
+      const v2d w = ldg<v2d>(b + (c * Vp + i) * 16);
       v[2 * c] = (T)w.x;
       v[2 * c + 1] = (T)w.y;
     }
@@ -141,16 +149,15 @@ template <> struct Fmt<F32> {
   using real = float;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    const float4* p = reinterpret_cast<const float4*>(b);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      float4 v = p[k * Vp + i];
+      const v4f v = ldg<v4f>(b + (k * Vp + i) * 16);
       m[4 * k] = v.x;
       m[4 * k + 1] = v.y;
       m[4 * k + 2] = v.z;
       m[4 * k + 3] = v.w;
     }
-    float2 v = reinterpret_cast<const float2*>(b + 64 * Vp)[i];
+    const v2f v = ldg<v2f>(b + 64 * Vp + i * 8);
     m[16] = v.x;
     m[17] = v.y;
   }
@@ -163,8 +170,8 @@ template <> struct Fmt<F32> {
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
-    float4 a = reinterpret_cast<const float4*>(b)[i];
-    float2 c = reinterpret_cast<const float2*>(b + 16 * Vp)[i];
+    const v4f a = ldg<v4f>(b + i * 16);
+    const v2f c = ldg<v2f>(b + 16 * Vp + i * 8);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y;
   }
   template <typename T, bool NT = false>
@@ -179,9 +186,9 @@ template <> struct Fmt<F16S> {
   using real = float;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
-    uint4 p1 = reinterpret_cast<const uint4*>(b + 16 * Vp)[i];
-    uint2 p2 = reinterpret_cast<const uint2*>(b + 32 * Vp)[i];
+    const v4u p0 = ldg<v4u>(b + i * 16);
+    const v4u p1 = ldg<v4u>(b + 16 * Vp + i * 16);
+    const v2u p2 = ldg<v2u>(b + 32 * Vp + i * 8);
     const float s = __uint_as_float(p2.y);
     const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
 #pragma unroll
@@ -206,7 +213,7 @@ template <> struct Fmt<F16S> {
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
     (void)Vp;
-    uint4 p = reinterpret_cast<const uint4*>(b)[i];
+    const v4u p = ldg<v4u>(b + i * 16);
     const float s = __uint_as_float(p.w);
     v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
     v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
@@ -238,9 +245,9 @@ template <> struct Fmt<BF16> {
   using real = float;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
-    uint4 p1 = reinterpret_cast<const uint4*>(b + 16 * Vp)[i];
-    uint32_t p2 = reinterpret_cast<const uint32_t*>(b + 32 * Vp)[i];
+    const v4u p0 = ldg<v4u>(b + i * 16);
+    const v4u p1 = ldg<v4u>(b + 16 * Vp + i * 16);
+    const uint32_t p2 = ldg<uint32_t>(b + 32 * Vp + i * 4);
     const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2};
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -258,8 +265,8 @@ template <> struct Fmt<BF16> {
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
-    uint2 p = reinterpret_cast<const uint2*>(b)[i];
-    uint32_t q = reinterpret_cast<const uint32_t*>(b + 8 * Vp)[i];
+    const v2u p = ldg<v2u>(b + i * 8);
+    const uint32_t q = ldg<uint32_t>(b + 8 * Vp + i * 4);
     v[0] = bf16_to_f32(p.x & 0xffffu); v[1] = bf16_to_f32(p.x >> 16);
     v[2] = bf16_to_f32(p.y & 0xffffu); v[3] = bf16_to_f32(p.y >> 16);
     v[4] = bf16_to_f32(q & 0xffffu);   v[5] = bf16_to_f32(q >> 16);
@@ -276,10 +283,9 @@ template <> struct Fmt<BF16> {
 template <> struct Fmt<F64 | W12> : Fmt<F64> {
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    const double2* p = reinterpret_cast<const double2*>(b);
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-      double2 v = p[k * Vp + i];
+      const v2d v = ldg<v2d>(b + (k * Vp + i) * 16);
       m[2 * k] = (T)v.x;
       m[2 * k + 1] = (T)v.y;
     }
@@ -295,10 +301,9 @@ template <> struct Fmt<F64 | W12> : Fmt<F64> {
 template <> struct Fmt<F32 | W12> : Fmt<F32> {
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    const float4* p = reinterpret_cast<const float4*>(b);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      float4 v = p[k * Vp + i];
+      const v4f v = ldg<v4f>(b + (k * Vp + i) * 16);
       m[4 * k] = v.x;
       m[4 * k + 1] = v.y;
       m[4 * k + 2] = v.z;
@@ -319,8 +324,8 @@ template <uint32_t (*Pack)(float, float), float (*Unpack)(uint32_t)>
 struct Fmt16W12 {
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
-    const uint4 p0 = reinterpret_cast<const uint4*>(b)[i];
-    const uint2 p1 = reinterpret_cast<const uint2*>(b + 16 * Vp)[i];
+    const v4u p0 = ldg<v4u>(b + i * 16);
+    const v2u p1 = ldg<v2u>(b + 16 * Vp + i * 8);
     const uint32_t w[6] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y};
 #pragma unroll
     for (int k = 0; k < 6; k++) {
@@ -383,7 +388,7 @@ template <> struct Planes<F64> : FullW<Planes<F64>, 9> {
   static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-      const double2 v = *reinterpret_cast<const double2*>(pl[k] + i * 16u);
+      const v2d v = ldg<v2d>(pl[k] + i * 16u);
       m[2 * k] = (T)v.x;
       m[2 * k + 1] = (T)v.y;
     }
@@ -397,7 +402,7 @@ template <> struct Planes<F64> : FullW<Planes<F64>, 9> {
   static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      const double2 w = *reinterpret_cast<const double2*>(pl[c] + i * 16u);
+      const v2d w = ldg<v2d>(pl[c] + i * 16u);
       v[2 * c] = (T)w.x;
       v[2 * c + 1] = (T)w.y;
     }
@@ -419,13 +424,13 @@ template <> struct Planes<F32> : FullW<Planes<F32>, 5> {
   static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const float4 v = *reinterpret_cast<const float4*>(pl[k] + i * 16u);
+      const v4f v = ldg<v4f>(pl[k] + i * 16u);
       m[4 * k] = v.x;
       m[4 * k + 1] = v.y;
       m[4 * k + 2] = v.z;
       m[4 * k + 3] = v.w;
     }
-    const float2 v = *reinterpret_cast<const float2*>(pl[4] + i * 8u);
+    const v2f v = ldg<v2f>(pl[4] + i * 8u);
     m[16] = v.x;
     m[17] = v.y;
   }
@@ -436,8 +441,8 @@ template <> struct Planes<F32> : FullW<Planes<F32>, 5> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
-    const float4 a = *reinterpret_cast<const float4*>(pl[0] + i * 16u);
-    const float2 c = *reinterpret_cast<const float2*>(pl[1] + i * 8u);
+    const v4f a = ldg<v4f>(pl[0] + i * 16u);
+    const v2f c = ldg<v2f>(pl[1] + i * 8u);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y;
   }
   template <typename T, bool NT>
@@ -456,9 +461,9 @@ template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
-    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
-    const uint4 p1 = *reinterpret_cast<const uint4*>(pl[1] + i * 16u);
-    const uint2 p2 = *reinterpret_cast<const uint2*>(pl[2] + i * 8u);
+    const v4u p0 = ldg<v4u>(pl[0] + i * 16u);
+    const v4u p1 = ldg<v4u>(pl[1] + i * 16u);
+    const v2u p2 = ldg<v2u>(pl[2] + i * 8u);
     const float s = __uint_as_float(p2.y);
     const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
 #pragma unroll
@@ -474,7 +479,7 @@ template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
-    const uint4 p = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
+    const v4u p = ldg<v4u>(pl[0] + i * 16u);
     const float s = __uint_as_float(p.w);
     v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
     v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
@@ -508,9 +513,9 @@ template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_w(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
-    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
-    const uint4 p1 = *reinterpret_cast<const uint4*>(pl[1] + i * 16u);
-    const uint32_t p2 = *reinterpret_cast<const uint32_t*>(pl[2] + i * 4u);
+    const v4u p0 = ldg<v4u>(pl[0] + i * 16u);
+    const v4u p1 = ldg<v4u>(pl[1] + i * 16u);
+    const uint32_t p2 = ldg<uint32_t>(pl[2] + i * 4u);
     const uint32_t w[9] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2};
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -525,8 +530,8 @@ template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
-    const uint2 p = *reinterpret_cast<const uint2*>(pl[0] + i * 8u);
-    const uint32_t q = *reinterpret_cast<const uint32_t*>(pl[1] + i * 4u);
+    const v2u p = ldg<v2u>(pl[0] + i * 8u);
+    const uint32_t q = ldg<uint32_t>(pl[1] + i * 4u);
     v[0] = bf16_to_f32(p.x & 0xffffu); v[1] = bf16_to_f32(p.x >> 16);
     v[2] = bf16_to_f32(p.y & 0xffffu); v[3] = bf16_to_f32(p.y >> 16);
     v[4] = bf16_to_f32(q & 0xffffu);   v[5] = bf16_to_f32(q >> 16);
@@ -555,7 +560,7 @@ template <> struct Planes<F64 | W12> : PlanesW12<Planes<F64>, 6> {
   static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-      const double2 v = *reinterpret_cast<const double2*>(pl[k] + i * 16u);
+      const v2d v = ldg<v2d>(pl[k] + i * 16u);
       m[2 * k] = (T)v.x;
       m[2 * k + 1] = (T)v.y;
     }
@@ -572,7 +577,7 @@ template <> struct Planes<F32 | W12> : PlanesW12<Planes<F32>, 3> {
   static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      const float4 v = *reinterpret_cast<const float4*>(pl[k] + i * 16u);
+      const v4f v = ldg<v4f>(pl[k] + i * 16u);
       m[4 * k] = v.x;
       m[4 * k + 1] = v.y;
       m[4 * k + 2] = v.z;
@@ -591,8 +596,8 @@ struct Planes16W12 : PlanesW12<Base, 2> {
   static constexpr int NW = 2;
   template <typename T>
   static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
-    const uint4 p0 = *reinterpret_cast<const uint4*>(pl[0] + i * 16u);
-    const uint2 p1 = *reinterpret_cast<const uint2*>(pl[1] + i * 8u);
+    const v4u p0 = ldg<v4u>(pl[0] + i * 16u);
+    const v2u p1 = ldg<v2u>(pl[1] + i * 8u);
     const uint32_t w[6] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y};
 #pragma unroll
     for (int k = 0; k < 6; k++) {

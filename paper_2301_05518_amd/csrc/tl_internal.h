@@ -39,7 +39,7 @@ struct StepGroup {
   int32_t n_xy_tiles;     // ceil(Lx*Ly / block)
   int32_t n_z_tiles;      // ceil(Lz / tz)
   int32_t tile_begin;     // work-list index of the group's first tile
-  int32_t rows;           // variants 5, 6: full rows of the xy plane per tile (divides Ly)
+  int32_t rows;           // variants 5-7: full rows of the xy plane per tile (divides Ly)
 };
 
 // Launch configuration of the step kernel.
@@ -55,14 +55,16 @@ struct StepConfig {
                  //    exchanged through LDS (fewer vector-memory instructions)
                  // 6: as 5, marching chains of planes z, z+2, ... (smaller rings; the
                  //    in-plane two-links are loaded before the LDS barrier)
-  int block;     // threads per workgroup (xy sites per tile; variant 5: an upper bound)
+                 // 7: as 6, software-pipelined: each plane step issues the next step's
+                 //    loads into the registers its own arithmetic has just freed
+  int block;     // threads per workgroup (xy sites per tile; variants 5-7: an upper bound)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile
   int nt;        // 1: nontemporal output stores (pays when a step's working set exceeds the
                  // Infinity Cache; costs when the next step could have re-read it from there)
 };
 
-// Rows per tile of variant 5 for an Lx x Ly plane and a block size: the largest divisor of Ly
+// Rows per tile of variants 5-7 for an Lx x Ly plane and a block size: the largest divisor of Ly
 // with rows * Lx <= block and rows >= 4 (0 if there is none).
 inline int lds_rows(int Lx, int Ly, int block) {
   for (int r = block / Lx; r >= 4; r--)
@@ -70,7 +72,7 @@ inline int lds_rows(int Lx, int Ly, int block) {
   return 0;
 }
 
-// Dynamic LDS bytes variants 5 and 6 need for a group: two buffers of (rows + 4) rows of R vectors.
+// Dynamic LDS bytes variants 5-7 need for a group: two buffers of (rows + 4) rows of R vectors.
 inline int64_t lds_bytes(int code, int R, int Lx, int rows) {
   return 2LL * (rows + 4) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
 }
@@ -79,8 +81,8 @@ inline int64_t lds_bytes(int code, int R, int Lx, int rows) {
 hipError_t init_kernel_attributes();
 
 // psi_out = alpha psi_in + beta sum_hops on every tile in [tile_base, tile_base + n_tiles).
-// code: format code (precision, optionally | W12).  lds: dynamic LDS bytes for variants 5
-// and 6 (max over the groups), 0 otherwise.
+// code: format code (precision, optionally | W12).  lds: dynamic LDS bytes for variants
+// 5-7 (max over the groups), 0 otherwise.
 hipError_t launch_step(int code, int width, const StepConfig& cfg, const StepGroup* groups,
                        int n_groups, int tile_base, int n_tiles, const char* in, char* out,
                        double alpha, double beta, int64_t lds, hipStream_t stream);

@@ -234,7 +234,7 @@ hipError_t launch_step(int code, int width, const StepConfig& cfg, const StepGro
                        int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta, int64_t lds,
                        hipStream_t stream) {
   if (n_tiles <= 0) return hipSuccess;
-  const int max_block = (cfg.variant == 5 || cfg.variant == 6) ? 512 : 256;
+  const int max_block = cfg.variant >= 5 ? 512 : 256;
   if (cfg.block < 64 || cfg.block > max_block || cfg.block % 64 != 0 || cfg.tz < 1) return hipErrorInvalidValue;
   if (code < 0 || code > (BF16 | W12)) return hipErrorInvalidValue;
   const bool w = is_w12(code);

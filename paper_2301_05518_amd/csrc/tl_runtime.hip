@@ -258,7 +258,7 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
     s.Lz = g.L[2];
     s.Vp = (int32_t)jc.Vp;
     s.nr = gr.nr;
-    if (cfg.variant == 5 || cfg.variant == 6) {
+    if (cfg.variant >= 5) {   // full-row tiles
       s.rows = tl::lds_rows(g.L[0], g.L[1], cfg.block);
       if (s.rows == 0) return TL_ERR_UNSUPPORTED;
       s.n_xy_tiles = g.L[1] / s.rows;
@@ -266,7 +266,7 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
       s.rows = 0;
       s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
     }
-    if (cfg.variant == 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd
+    if (cfg.variant >= 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd
       const int chains = (g.L[2] & 1) ? 1 : 2;
       const int clen = g.L[2] / chains;
       s.n_z_tiles = chains * ((clen + cfg.tz - 1) / cfg.tz);
@@ -284,7 +284,7 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
 
 // Dynamic LDS bytes of a configuration (variant 5), -1 if it does not fit.
 int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<StepGroup>& gs) {
-  if (cfg.variant != 5 && cfg.variant != 6) return 0;
+  if (cfg.variant < 5) return 0;
   int64_t mx = 0;
   const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
   for (const auto& g : gs) mx = std::max(mx, tl::lds_bytes(p->prec, R, g.Lx, g.rows));
@@ -292,7 +292,7 @@ int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<Step
 }
 
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
-  if ((cfg.variant == 5 || cfg.variant == 6) && tl::vprec(p->prec) == tl::F64 && p->width > 1)
+  if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1)
     return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernels take FP64 groups of one RHS only");
   std::vector<StepGroup> gs;
   if (make_groups(p, cfg, &gs) != TL_OK)
@@ -365,12 +365,12 @@ int plan_autotune(tl_plan* p) {
   }
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
-  for (int variant : {0, 2, 3, 4, 5, 6}) {
-    const bool lds_variant = variant == 5 || variant == 6;
+  for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
+    const bool lds_variant = variant >= 5;
     if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && p->width > 1) continue;   // would run variant 0
     if (lds_variant && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
-                                 : (variant == 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
+                                 : (variant >= 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
     const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 64};
     for (int block : blocks)
       for (int tz : tzs)
@@ -393,7 +393,7 @@ int plan_autotune(tl_plan* p) {
   const int reps = 10;
   for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
     p->cfg = cands[ci];
-    if (p->cfg.variant == 5 || p->cfg.variant == 6) {   // only where every lattice has a row tiling that fits in LDS
+    if (p->cfg.variant >= 5) {   // only where every lattice has a row tiling that fits in LDS
       std::vector<StepGroup> gs;
       if (make_groups(p, p->cfg, &gs) != TL_OK || plan_lds(p, p->cfg, gs) < 0) continue;
     }
@@ -455,7 +455,7 @@ bool tile_override(StepConfig* cfg) {
   if (n < 4) return false;
   if (n == 4) c.nt = 0;
   if (c.nt != 0 && c.nt != 1) return false;
-  if (c.variant < 0 || c.variant > 6 || c.block < 64 || c.block > (c.variant >= 5 ? 512 : 256) || c.block % 64 || c.tz < 1) return false;
+  if (c.variant < 0 || c.variant > 7 || c.block < 64 || c.block > (c.variant >= 5 ? 512 : 256) || c.block % 64 || c.tz < 1) return false;
   *cfg = c;
   return true;
 }

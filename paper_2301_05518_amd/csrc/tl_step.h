@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "tl_format.h"
 #include "tl_internal.h"
@@ -997,6 +998,199 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
   }
 }
 
+// Variant 7: variant 6 software-pipelined across plane steps.  The waves of a
+// workgroup meet at the LDS barrier every step, so they all wait for memory at
+// the same time unless a step's loads are issued a step early.  Each step
+// therefore issues, right after its in-plane hops, the next plane's in-plane
+// two-links and halo rows (into the registers those hops just freed), and after
+// its store the next plane's colour vectors ahead in the march and its z
+// two-link (into the ring slots the z hops just freed).  The arithmetic and its
+// order are those of variant 6.
+template <int P, int R, bool NT>
+__global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ groups, int n_groups,
+                                                  int tile_base, int n_tiles, int tz,
+                                                  const char* __restrict__ in, char* __restrict__ out,
+                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
+  using c2 = typename Complex2<real>::type;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  c2* const lds = reinterpret_cast<c2*>(lds_raw);
+  const TileSweep sw = xcd_sweep(n_tiles);
+  int it = 0;
+  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+    const int tile = tile_base + tl;
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;          // chain chunk index: n_z_tiles = chains * chunks
+    const int y0 = (local - tzi * g.n_xy_tiles) * rows;
+    const int chains = (Lz & 1) ? 1 : 2;
+    const int clen = Lz / chains;                  // planes per chain
+    const int chunks = (clen + tz - 1) / tz;
+    const int chain = tzi / chunks, chunk = tzi - chain * chunks;
+    const int LxLy = Lx * Ly;
+    const int t = (int)threadIdx.x;
+    const int trow = t / Lx, x = t - trow * Lx;
+    const bool active = trow < rows;
+    const int row = active ? trow : 0;
+    const int y = y0 + row;
+    const int xy = y * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - 2, Lx);
+    const int ybw = wrap_sel(y - 2, Ly) * Lx + x;
+    const int nsite = (rows + 4) * Lx;
+    const int own = (row + 2) * Lx + x;
+    const int sxf = (row + 2) * Lx + wrap_sel(x + 2, Lx), sxb = (row + 2) * Lx + wrap_sel(x - 2, Lx);
+    const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
+    const bool halo = t < 4 * Lx;
+    const int hr = halo ? trow : 0;
+    const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;
+    const int hxy = wrap_sel(y0 + hrho, Ly) * Lx + x;
+    const int hslot = (hrho + 2) * Lx + x;
+    const char* wp[3][PL::NW];
+#pragma unroll
+    for (int mu = 0; mu < 3; mu++) PL::w(g.W + mu * g.w_mu_stride, Vp, wp[mu]);
+    const int nr = g.nr;
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
+    }
+    const int k0 = chunk * tz;
+    const int nz = min(k0 + tz, clen) - k0;        // planes of this chunk
+    const bool up = (chunk & 1) == 0;
+    const int kf = up ? k0 : k0 + nz - 1;
+    int z = wrap_sel(chain + 2 * kf, Lz);
+    const int step = up ? 2 : -2;
+    // ring[0]: plane behind in the march, ring[1]: current, ring[2]: ahead.
+    // wz[1]: the z two-link loaded for the current plane (W_z(z) marching up, W_z(z-2)
+    // marching down), wz[0]: the one loaded for the previous plane.
+    real ring[3][R][6];
+    real wz[2][18];
+    real mxf[18], mxb[18], myf[18], myb[18];
+    real hv[R][6];
+    {
+      const uint32_t zo = (uint32_t)(z * LxLy);
+      const uint32_t zc = zo + xy;
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        PL::load_v(ip[r], (uint32_t)(wrap_sel(z - step, Lz) * LxLy + xy), ring[0][r]);
+        PL::load_v(ip[r], zc, ring[1][r]);
+        PL::load_v(ip[r], (uint32_t)(wrap_sel(z + step, Lz) * LxLy + xy), ring[2][r]);
+        PL::load_v(ip[r], zo + hxy, hv[r]);
+      }
+      const uint32_t zm = (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy);
+      PL::load_w(wp[2], up ? zm : zc, wz[0]);
+      PL::load_w(wp[2], up ? zc : zm, wz[1]);
+      PL::load_w_raw(wp[0], zc, mxf);
+      PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
+      PL::load_w_raw(wp[1], zc, myf);
+      PL::load_w_raw(wp[1], zo + (uint32_t)ybw, myb);
+    }
+    // one plane step; MORE: a further plane follows in this chunk (the last step is
+    // peeled off, so the loads for a next plane are unconditional inside the loop and
+    // the registers they overwrite are not kept alive)
+    auto plane_step = [&](auto more_c) {
+      constexpr bool MORE = decltype(more_c)::value;
+      const uint32_t site = (uint32_t)(z * LxLy) + xy;
+      const int zn = wrap_sel(z + step, Lz);        // next plane of the march
+      const uint32_t zno = (uint32_t)(zn * LxLy);
+      c2* const buf = lds + (it & 1) * (R * 3) * nsite;
+      if (halo) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
+      }
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[1][r][2 * c], ring[1][r][2 * c + 1]};
+      }
+      __syncthreads();
+      PL::finish_w(mxf);
+      PL::finish_w(mxb);
+      PL::finish_w(myf);
+      PL::finish_w(myb);
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+        real v[6];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + sxf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(mxf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + sxb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(mxb, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(myf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(myb, v, acc[r]);
+      }
+      // keep the next plane's loads below the hops that free their registers
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {   // next plane: in-plane two-links and halo rows
+        PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
+        PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+        PL::load_w_raw(wp[1], zno + (uint32_t)xy, myf);
+        PL::load_w_raw(wp[1], zno + (uint32_t)ybw, myb);
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], zno + (uint32_t)hxy, hv[r]);
+      }
+      // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
+      if (up) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          mv_acc(wz[1], ring[2][r], acc[r]);
+          mdv_acc(wz[0], ring[0][r], acc[r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          mv_acc(wz[0], ring[0][r], acc[r]);
+          mdv_acc(wz[1], ring[2][r], acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[1][r][c]);
+        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {   // next plane: colour vectors ahead of it and its z two-link
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 6; c++) {
+            ring[0][r][c] = ring[1][r][c];
+            ring[1][r][c] = ring[2][r][c];
+          }
+#pragma unroll
+        for (int c = 0; c < 18; c++) wz[0][c] = wz[1][c];
+        const int za = wrap_sel(zn + step, Lz);
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ring[2][r]);
+        PL::load_w(wp[2], up ? zno + (uint32_t)xy : (uint32_t)(wrap_sel(zn - 2, Lz) * LxLy + xy), wz[1]);
+      }
+      z = zn;
+      it++;
+    };
+    for (int i = 0; i + 1 < nz; i++) plane_step(std::true_type{});
+    plane_step(std::false_type{});
+  }
+}
+
 constexpr int kMaxLds = 160 * 1024;   // LDS per compute unit on gfx950
 
 template <int P, int R, bool NT>
@@ -1009,9 +1203,9 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   // groups runs the direct kernel, which computes the same bits.
   // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
   // never selects it for FP64 groups wider than one RHS)
-  if ((cfg.variant == 5 || cfg.variant == 6) && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
+  if (cfg.variant >= 5 && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
   const bool direct = cfg.variant == 0 || (vprec(P) == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
-                                           cfg.variant != 5 && cfg.variant != 6);
+                                           cfg.variant < 5);
   (void)lds;
   constexpr int R1 = (vprec(P) == F64 && R > 2) ? 1 : R;
   constexpr int R2 = (vprec(P) == F64) ? 1 : R;
@@ -1026,7 +1220,11 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
     step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
   else if (cfg.variant == 4)
     step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
-  else if (cfg.variant == 6) {
+  else if (cfg.variant == 7) {
+    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+    step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+                                                              a, b);
+  } else if (cfg.variant == 6) {
     if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
     step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
                                                                a, b);
@@ -1053,7 +1251,9 @@ hipError_t allow_lds() {
   for (const void* f : {reinterpret_cast<const void*>(&step_zlds<P, R, false>),
                         reinterpret_cast<const void*>(&step_zlds<P, R, true>),
                         reinterpret_cast<const void*>(&step_zchain<P, R, false>),
-                        reinterpret_cast<const void*>(&step_zchain<P, R, true>)}) {
+                        reinterpret_cast<const void*>(&step_zchain<P, R, true>),
+                        reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
+                        reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     if (e != hipSuccess) return e;
   }
