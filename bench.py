@@ -332,7 +332,7 @@ def main():
             "storage": prec,
             "accumulate": "f64" if wl.precisions[0] == "f64" else "f32",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
-            "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "n_tiles", "group_width")},
+            "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip", "n_tiles", "group_width")},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -120,6 +120,7 @@ typedef struct {
     int32_t tz;                /* z planes per tile */
     int32_t grid;              /* workgroups per step launch */
     int32_t nt;                /* 1: nontemporal output stores */
+    int32_t flip;              /* 1: odd steps run in reversed tile and march order */
     int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN */
     int64_t rhs_sites;         /* sum over RHS of Lx*Ly*Lz */
     double bytes_per_step;     /* algorithmic bytes of one step: W once per group + psi in and out */
@@ -134,7 +135,7 @@ int tl_version(void);
 
 /*
  * Environment (read by the library):
- *   TL_TILE="variant,block,tz,grid[,nt]"  fix the step tiling of every plan (no tuning);
+ *   TL_TILE="variant,block,tz,grid[,nt[,flip]]"  fix the step tiling of every plan (no tuning);
  *                                    for profiling and sweeps
  *   TL_LOG=1                         print autotuning candidates to stderr
  *   TL_FAULT=alloc|launch            make internal allocations or launches fail

@@ -62,6 +62,10 @@ struct StepConfig {
   int grid;      // workgroups; <= 0 means one workgroup per tile
   int nt;        // 1: nontemporal output stores (pays when a step's working set exceeds the
                  // Infinity Cache; costs when the next step could have re-read it from there)
+  int flip;      // 1: odd steps of a sequence run reversed (tile order and march directions),
+                 // so a step starts on the planes the previous step touched last, which are
+                 // still in the Infinity Cache when a step's working set exceeds it
+  int rev;       // set per launch: this launch runs reversed
 };
 
 // Rows per tile of variants 5-7 for an Lx x Ly plane and a block size: the largest divisor of Ly

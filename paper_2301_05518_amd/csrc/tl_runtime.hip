@@ -308,15 +308,18 @@ int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
 }
 
 // One step over every group (batched) or over one group (plain mode, g >= 0).
-int plan_step(tl_plan* p, hipStream_t s, int parity, int g) {
+// k: index of the step in its sequence (odd steps run reversed when the tiling flips).
+int plan_step(tl_plan* p, hipStream_t s, int parity, int g, int k) {
   tl_ctx* c = p->ctx;
   int base = 0, n = p->n_tiles;
   if (g >= 0) {
     base = p->groups_host[g].tile_begin;
     n = p->groups_host[g].n_xy_tiles * p->groups_host[g].n_z_tiles;
   }
+  StepConfig cfg = p->cfg;
+  cfg.rev = (cfg.flip && (k & 1)) ? 1 : 0;
   return launch(c, "smearing step", [&] {
-    return tl::launch_step(p->prec, p->width, p->cfg, p->groups_dev, (int)p->groups_host.size(), base, n,
+    return tl::launch_step(p->prec, p->width, cfg, p->groups_dev, (int)p->groups_host.size(), base, n,
                            p->buf[parity], p->buf[parity ^ 1], p->alpha, p->beta, p->lds, s);
   });
 }
@@ -327,14 +330,14 @@ int plan_enqueue(tl_plan* p, hipStream_t s, int parity) {
     for (int g = 0; g < (int)p->groups_host.size(); g++) {
       int q = parity;
       for (int k = 0; k < p->n_steps; k++) {
-        TL_TRY(plan_step(p, s, q, g));
+        TL_TRY(plan_step(p, s, q, g, k));
         q ^= 1;
       }
     }
   } else {
     int q = parity;
     for (int k = 0; k < p->n_steps; k++) {
-      TL_TRY(plan_step(p, s, q, -1));
+      TL_TRY(plan_step(p, s, q, -1, k));
       q ^= 1;
     }
   }
@@ -375,7 +378,8 @@ int plan_autotune(tl_plan* p) {
     for (int block : blocks)
       for (int tz : tzs)
         for (int grid : {0, 8 * cu})
-          for (int nt : {0, 1}) cands.push_back({variant, block, tz, grid, nt});
+          for (int nt : {0, 1})
+            for (int flip : {0, 1}) cands.push_back({variant, block, tz, grid, nt, flip, 0});
   }
   void* ref = nullptr;
   void* flag_mem = nullptr;
@@ -400,10 +404,10 @@ int plan_autotune(tl_plan* p) {
     rc = plan_upload_groups(p, p->cfg);
     if (rc != TL_OK) break;
     const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
-    for (int w = 0; w < 2 && rc == TL_OK; w++) rc = plan_step(p, c->stream, p->cur, g_lim);
+    for (int w = 0; w < 2 && rc == TL_OK; w++) rc = plan_step(p, c->stream, p->cur, g_lim, w);
     if (rc != TL_OK) break;
     (void)hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps && rc == TL_OK; k++) rc = plan_step(p, c->stream, p->cur, g_lim);
+    for (int k = 0; k < reps && rc == TL_OK; k++) rc = plan_step(p, c->stream, p->cur, g_lim, k);
     (void)hipEventRecord(e1, c->stream);
     if (rc != TL_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -426,8 +430,8 @@ int plan_autotune(tl_plan* p) {
       same = one == 0;
     }
     if (c->log)
-      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d: %.4f ms/step%s\n",
-              key.c_str(), p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, p->cfg.nt, ms / reps,
+      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d flip=%d: %.4f ms/step%s\n",
+              key.c_str(), p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, p->cfg.nt, p->cfg.flip, ms / reps,
               same ? "" : "  OUTPUT DIFFERS - rejected");
     if (same && ms < best) {
       best = ms;
@@ -451,10 +455,11 @@ bool tile_override(StepConfig* cfg) {
   const char* e = getenv("TL_TILE");
   if (!e) return false;
   StepConfig c{};
-  const int n = sscanf(e, "%d,%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid, &c.nt);
+  const int n = sscanf(e, "%d,%d,%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid, &c.nt, &c.flip);
   if (n < 4) return false;
-  if (n == 4) c.nt = 0;
-  if (c.nt != 0 && c.nt != 1) return false;
+  if (n < 5) c.nt = 0;
+  if (n < 6) c.flip = 0;
+  if ((c.nt != 0 && c.nt != 1) || (c.flip != 0 && c.flip != 1)) return false;
   if (c.variant < 0 || c.variant > 7 || c.block < 64 || c.block > (c.variant >= 5 ? 512 : 256) || c.block % 64 || c.tz < 1) return false;
   *cfg = c;
   return true;
@@ -516,7 +521,7 @@ void plan_free(tl_plan* p) {
 
 extern "C" {
 
-int tl_version(void) { return 10000; }
+int tl_version(void) { return 10100; }
 
 int tl_create(tl_ctx** out, int device, void* stream) {
   if (!out) return fail(nullptr, TL_ERR_ARG, "out is NULL");
@@ -930,6 +935,7 @@ int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
   info->tz = p->cfg.tz;
   info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
   info->nt = p->cfg.nt;
+  info->flip = p->cfg.flip;
   return TL_OK;
 }
 

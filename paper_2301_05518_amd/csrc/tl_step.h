@@ -29,12 +29,15 @@ constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, each with its 
 // XCD b % 8).  Give the workgroups of one XCD a contiguous range of the work
 // list and let them sweep it together, so neighbouring tiles (which share
 // halo sites and two-links) meet in the same L2.  Correctness does not
-// depend on the dispatch order.
+// depend on the dispatch order.  rev: visit this workgroup's tiles in the
+// opposite order (steps alternate, see StepConfig::flip).
 struct TileSweep {
-  int first, stride, end;
+  int first, stride, n;
+  bool rev;
+  __device__ __forceinline__ int tile(int m) const { return first + (rev ? n - 1 - m : m) * stride; }
 };
 
-__device__ __forceinline__ TileSweep xcd_sweep(int n_tiles) {
+__device__ __forceinline__ TileSweep xcd_sweep(int n_tiles, int rev) {
   const int G = gridDim.x, b = blockIdx.x;
   const int k = b % kXcds, j = b / kXcds;
   const int q = G / kXcds, r = G % kXcds;
@@ -42,7 +45,8 @@ __device__ __forceinline__ TileSweep xcd_sweep(int n_tiles) {
   const int ord0 = k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q;  // their first ordinal
   const int t0 = (int)(((int64_t)n_tiles * ord0) / G);
   const int t1 = (int)(((int64_t)n_tiles * (ord0 + cnt)) / G);
-  return {t0 + j, cnt, t1};
+  const int first = t0 + j;
+  return {first, cnt, first < t1 ? (t1 - first + cnt - 1) / cnt : 0, rev != 0};
 }
 
 // v mod L for v in [-2L, 3L), branch-free
@@ -114,15 +118,16 @@ __device__ __forceinline__ int find_group(const StepGroup* __restrict__ groups, 
 // z planes; every neighbour value comes through L1/L2.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__ groups, int n_groups,
-                                                   int tile_base, int n_tiles, int tz,
+                                                   int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
   constexpr int VB = kVBytes[P];
   (void)VB;
-  const TileSweep sw = xcd_sweep(n_tiles);
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
@@ -197,13 +202,14 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
 // z hops and the centre term read no memory; one new plane is loaded per step.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__ groups, int n_groups,
-                                                   int tile_base, int n_tiles, int tz,
+                                                   int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
-  const TileSweep sw = xcd_sweep(n_tiles);
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
@@ -306,13 +312,14 @@ __global__ __launch_bounds__(256) void step_zmarch(const StepGroup* __restrict__
 // L2 for the second reader.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ groups, int n_groups,
-                                                  int tile_base, int n_tiles, int tz,
+                                                  int tile_base, int n_tiles, int tz, int rev,
                                                   const char* __restrict__ in, char* __restrict__ out,
                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
-  const TileSweep sw = xcd_sweep(n_tiles);
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
@@ -340,7 +347,7 @@ __global__ __launch_bounds__(256) void step_zring(const StepGroup* __restrict__ 
     }
     const int zlo = tzi * tz;
     const int nz = min(zlo + tz, Lz) - zlo;
-    const bool up = (tzi & 1) == 0;
+    const bool up = ((tzi & 1) == 0) != (rev != 0);
     const int dz = up ? 1 : -1;
     const int zs = up ? zlo : zlo + nz - 1;       // first plane of the march
     // ring[k] holds plane zs + dz*(k-2) relative to the current plane, i.e. k = 2 is
@@ -477,13 +484,14 @@ __device__ __forceinline__ void inplane_hops(const char* const (&Wmu)[3], const 
 // the site.  Chunks alternate their march direction as in variant 2.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__ groups, int n_groups,
-                                                   int tile_base, int n_tiles, int tz,
+                                                   int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
-  const TileSweep sw = xcd_sweep(n_tiles);
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
@@ -509,7 +517,7 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
     }
     const int zlo = tzi * tz;
     const int nz = min(zlo + tz, Lz) - zlo;
-    const bool up = (tzi & 1) == 0;
+    const bool up = ((tzi & 1) == 0) != (rev != 0);
     const int dz = up ? 1 : -1;
     const int zs = up ? zlo : zlo + nz - 1;
     real ring[5][R][6];      // own colour vectors, planes z-2dz .. z+2dz
@@ -579,13 +587,14 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
 // others' loads.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__ groups, int n_groups,
-                                                   int tile_base, int n_tiles, int tz,
+                                                   int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
-  const TileSweep sw = xcd_sweep(n_tiles);
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
@@ -668,7 +677,7 @@ template <> struct Complex2<double> { using type = double2; };
 // site offsets; plane wraps are branch-free.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ groups, int n_groups,
-                                                 int tile_base, int n_tiles, int tz,
+                                                 int tile_base, int n_tiles, int tz, int rev,
                                                  const char* __restrict__ in, char* __restrict__ out,
                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using PL = Planes<P>;
@@ -676,9 +685,10 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
   using c2 = typename Complex2<real>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   c2* const lds = reinterpret_cast<c2*>(lds_raw);
-  const TileSweep sw = xcd_sweep(n_tiles);
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
   int it = 0;   // steps done by this workgroup: selects the LDS buffer across tiles
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
@@ -718,7 +728,7 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
     }
     const int zlo = tzi * tz;
     const int nz = min(zlo + tz, Lz) - zlo;
-    const bool up = (tzi & 1) == 0;
+    const bool up = ((tzi & 1) == 0) != (rev != 0);
     const int dz = up ? 1 : -1;
     const int zs = up ? zlo : zlo + nz - 1;
     real ring[5][R][6];
@@ -836,7 +846,7 @@ __global__ __launch_bounds__(512) void step_zlds(const StepGroup* __restrict__ g
 // alternate their march direction along the chain.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__ groups, int n_groups,
-                                                   int tile_base, int n_tiles, int tz,
+                                                   int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using PL = Planes<P>;
@@ -844,9 +854,10 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
   using c2 = typename Complex2<real>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   c2* const lds = reinterpret_cast<c2*>(lds_raw);
-  const TileSweep sw = xcd_sweep(n_tiles);
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
   int it = 0;
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
@@ -890,7 +901,7 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
     }
     const int k0 = chunk * tz;
     const int nz = min(k0 + tz, clen) - k0;        // planes of this chunk
-    const bool up = (chunk & 1) == 0;
+    const bool up = ((chunk & 1) == 0) != (rev != 0);
     // first plane of the march: chain position k0 (up) or k0 + nz - 1 (down)
     const int kf = up ? k0 : k0 + nz - 1;
     int z = wrap_sel(chain + 2 * kf, Lz);          // kf < Lz, so the argument is below 3 Lz
@@ -1008,7 +1019,7 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
 // order are those of variant 6.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ groups, int n_groups,
-                                                  int tile_base, int n_tiles, int tz,
+                                                  int tile_base, int n_tiles, int tz, int rev,
                                                   const char* __restrict__ in, char* __restrict__ out,
                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using PL = Planes<P>;
@@ -1016,9 +1027,10 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
   using c2 = typename Complex2<real>::type;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   c2* const lds = reinterpret_cast<c2*>(lds_raw);
-  const TileSweep sw = xcd_sweep(n_tiles);
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
   int it = 0;
-  for (int tl = sw.first; tl < sw.end; tl += sw.stride) {
+  for (int m = 0; m < sw.n; m++) {
+    const int tl = sw.tile(m);
     const int tile = tile_base + tl;
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
     const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, rows = g.rows;
@@ -1062,7 +1074,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     }
     const int k0 = chunk * tz;
     const int nz = min(k0 + tz, clen) - k0;        // planes of this chunk
-    const bool up = (chunk & 1) == 0;
+    const bool up = ((chunk & 1) == 0) != (rev != 0);
     const int kf = up ? k0 : k0 + nz - 1;
     int z = wrap_sel(chain + 2 * kf, Lz);
     const int step = up ? 2 : -2;
@@ -1211,26 +1223,26 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   constexpr int R2 = (vprec(P) == F64) ? 1 : R;
   const real a = (real)alpha, b = (real)beta;
   if (direct)
-    step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+    step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
   else if (cfg.variant == 1)
-    step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+    step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
   else if (cfg.variant == 2)
-    step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+    step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
   else if (cfg.variant == 3)
-    step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+    step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
   else if (cfg.variant == 4)
-    step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out, a, b);
+    step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
   else if (cfg.variant == 7) {
     if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+    step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
                                                               a, b);
   } else if (cfg.variant == 6) {
     if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+    step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
                                                                a, b);
   } else if (cfg.variant == 5) {
     if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, in, out,
+    step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
                                                              a, b);
   } else
     return hipErrorInvalidValue;

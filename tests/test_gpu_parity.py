@@ -167,7 +167,10 @@ VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "1,128,5,512", "2,64,4,0
                  "4,64,1,0", "4,256,3,16", "4,128,2,0", "2,64,16,0,1", "0,64,2,0,1", "4,64,2,0,1",
                  "5,512,16,0", "5,256,3,0", "5,512,1,8", "5,256,5,0,1", "5,64,2,0",
                  "6,512,16,0", "6,256,3,0", "6,512,1,8", "6,256,2,0,1", "6,64,4,0",
-                 "7,512,16,0", "7,256,3,0", "7,512,1,8", "7,256,2,0,1", "7,64,4,0", "7,512,5,4"]
+                 "7,512,16,0", "7,256,3,0", "7,512,1,8", "7,256,2,0,1", "7,64,4,0", "7,512,5,4",
+                 # odd steps reversed (tile order and march directions)
+                 "0,64,2,5,0,1", "2,64,4,0,1,1", "3,128,5,0,0,1", "4,128,2,3,0,1", "5,256,3,0,1,1",
+                 "6,512,1,8,0,1", "7,512,16,0,1,1", "7,256,3,5,0,1"]
 
 
 @pytest.mark.parametrize("prec", PRECS)

@@ -89,7 +89,8 @@ def test_smear_w12(ctx, orc, torch, prec):
 
 VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "2,64,4,0", "2,128,3,0", "3,64,2,0", "3,128,5,0",
                  "4,64,1,0", "4,256,3,16", "5,512,16,0", "5,256,3,0", "5,256,5,0,1", "6,512,16,0",
-                 "6,256,3,0", "6,512,1,8", "6,256,2,0,1", "7,512,16,0", "7,256,3,0", "7,512,1,8", "7,256,2,0,1"]
+                 "6,256,3,0", "6,512,1,8", "6,256,2,0,1", "7,512,16,0", "7,256,3,0", "7,512,1,8", "7,256,2,0,1",
+                 "7,512,16,0,1,1", "5,256,5,0,0,1", "2,64,4,0,1,1"]
 
 
 @pytest.mark.parametrize("prec", W12)
