@@ -52,6 +52,22 @@ def free_kernel_dft(L3: Sequence[int], n: int, sigma: float, x0: Sequence[int] =
     return np.roll(k, shift=(x0[2], x0[1], x0[0]), axis=(0, 1, 2))
 
 
+def plane_wave_eigenvalue_onelink(k: Sequence[int], L3: Sequence[int]) -> float:
+    """Eigenvalue of the free one-link Laplacian H - 6 on exp(i p.x): -4 sum_mu sin^2(p_mu / 2)."""
+    return float(-4.0 * sum(np.sin(np.pi * k[i] / L3[i]) ** 2 for i in range(3)))
+
+
+def free_kernel_onelink_dft(L3: Sequence[int], n: int, sigma: float, x0: Sequence[int] = (0, 0, 0)) -> np.ndarray:
+    """Free-field point source after (1 + (sigma/n)(H - 6))^n, scalar profile [Lz][Ly][Lx]."""
+    Lx, Ly, Lz = _dims(L3)
+    s2 = (np.sin(np.pi * np.arange(Lz) / Lz)[:, None, None] ** 2
+          + np.sin(np.pi * np.arange(Ly) / Ly)[None, :, None] ** 2
+          + np.sin(np.pi * np.arange(Lx) / Lx)[None, None, :] ** 2)
+    lam = 1.0 - (sigma / n) * 4.0 * s2
+    k = np.fft.ifftn(lam ** n).real
+    return np.roll(k, shift=(x0[2], x0[1], x0[0]), axis=(0, 1, 2))
+
+
 def walk_counts(L: int, kmax: int) -> np.ndarray:
     """B[k, x] = number of k-step walks with steps +-2 from 0 ending at x (mod L)."""
     B = np.zeros((kmax + 1, L), dtype=np.float64)

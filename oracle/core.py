@@ -3,6 +3,8 @@
 All arrays are host numpy complex128 in the natural layouts documented in
 ``oracle.c``:  U [Lt][Lz][Ly][Lx][4][3][3], two-link field
 [Lt][Lz][Ly][Lx][3][3][3], one-slice colour vectors [Lz][Ly][Lx][3].
+Test infrastructure: only the tests, the package smoke check and the
+benchmark's CPU-baseline leg use it.
 """
 from __future__ import annotations
 
@@ -38,6 +40,11 @@ class Oracle:
         l.or_lap_oneplusone.argtypes = [_c_int4, vp, ctypes.c_int, vp, vp]
         l.or_smear.argtypes = [_c_int4, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp]
         l.or_smear_batch.argtypes = [_c_int4, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double, vp]
+        l.or_hop_onelink.argtypes = [_c_int4, vp, ctypes.c_int, vp, vp]
+        l.or_lap_onelink.argtypes = [_c_int4, vp, ctypes.c_int, vp, vp]
+        l.or_gsmear_hop.argtypes = [_c_int4, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp]
+        l.or_smear_onelink.argtypes = [_c_int4, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp]
+        l.or_smear_onelink_batch.argtypes = [_c_int4, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double, vp]
         l.or_norm2.argtypes = [ctypes.c_long, vp]
         l.or_norm2.restype = ctypes.c_double
         l.or_dot.argtypes = [ctypes.c_long, vp, vp, _dp, _dp]
@@ -99,6 +106,51 @@ class Oracle:
         ts = np.ascontiguousarray(t_of_rhs, dtype=np.int32)
         assert out.shape == (len(ts), L[2], L[1], L[0], 3)
         self.lib.or_smear_batch(g, _ptr(W), len(ts), _ptr(ts), int(n), float(sigma), _ptr(out))
+        return out
+
+    # -- one-link operators (Sec. 2: H, nabla^2 = H - 6, eq. gsmear)
+    def _slice_op(self, fn, U, t, psi):
+        U = self._c128(U)
+        psi = self._c128(psi)
+        g, L = self._geom(U)
+        assert U.shape[4:] == (4, 3, 3) and psi.shape == (L[2], L[1], L[0], 3)
+        out = np.empty_like(psi)
+        fn(g, _ptr(U), int(t), _ptr(psi), _ptr(out))
+        return out
+
+    def hop_onelink(self, U: np.ndarray, t: int, psi: np.ndarray) -> np.ndarray:
+        """H psi on slice t."""
+        return self._slice_op(self.lib.or_hop_onelink, U, t, psi)
+
+    def laplacian_onelink(self, U: np.ndarray, t: int, psi: np.ndarray) -> np.ndarray:
+        """nabla^2 psi = (H - 6) psi on slice t."""
+        return self._slice_op(self.lib.or_lap_onelink, U, t, psi)
+
+    def gsmear_hop(self, U: np.ndarray, t: int, n: int, alpha: float, psi: np.ndarray) -> np.ndarray:
+        """(1 + alpha H)^n psi on slice t (eq. gsmear without C)."""
+        U = self._c128(U)
+        out = self._c128(psi).copy()
+        g, L = self._geom(U)
+        assert out.shape == (L[2], L[1], L[0], 3)
+        self.lib.or_gsmear_hop(g, _ptr(U), int(t), int(n), float(alpha), _ptr(out))
+        return out
+
+    def smear_onelink(self, U: np.ndarray, t: int, n: int, sigma: float, psi: np.ndarray) -> np.ndarray:
+        """(1 + (sigma/n) nabla^2)^n psi on slice t."""
+        U = self._c128(U)
+        out = self._c128(psi).copy()
+        g, L = self._geom(U)
+        assert out.shape == (L[2], L[1], L[0], 3)
+        self.lib.or_smear_onelink(g, _ptr(U), int(t), int(n), float(sigma), _ptr(out))
+        return out
+
+    def smear_onelink_batch(self, U: np.ndarray, t_of_rhs, n: int, sigma: float, psi: np.ndarray) -> np.ndarray:
+        U = self._c128(U)
+        out = self._c128(psi).copy()
+        g, L = self._geom(U)
+        ts = np.ascontiguousarray(t_of_rhs, dtype=np.int32)
+        assert out.shape == (len(ts), L[2], L[1], L[0], 3)
+        self.lib.or_smear_onelink_batch(g, _ptr(U), len(ts), _ptr(ts), int(n), float(sigma), _ptr(out))
         return out
 
     # -- reductions

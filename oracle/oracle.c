@@ -20,7 +20,9 @@
  * Parity pins: every function here is checked by the CPU test suite against
  * closed forms, invariants and brute force (unit gauge, diagonal phases,
  * gauge covariance, Hermiticity, the free-field plane-wave spectrum, the
- * exact free-field smearing kernel, dense 4^3 matrices).
+ * exact free-field smearing kernel, dense 4^3 matrices; for the one-link
+ * operators also the identity between the hopping and Laplacian forms of
+ * Gaussian smearing that follows eq. gsmear).
  */
 #include <complex.h>
 #include <math.h>
@@ -221,6 +223,101 @@ void or_smear_batch(const int L[4], const cplx *W, int n_rhs, const int *t_of_rh
     long V3 = (long)L[0] * L[1] * L[2];
     for (int r = 0; r < n_rhs; r++)
         or_smear(L, W, t_of_rhs[r], n, sigma, psi + (long)r * 3 * V3);
+}
+
+/*
+ * One-link hopping operator H of Sec. 2 on slice t (three spatial directions):
+ *   (H psi)(x) = sum_mu [ U_mu(x) psi(x+mu^) + U_mu^dag(x-mu^) psi(x-mu^) ].
+ */
+void or_hop_onelink(const int L[4], const cplx *U, int t, const cplx *in, cplx *out)
+{
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < L[2]; z++)
+        for (int y = 0; y < L[1]; y++)
+            for (int x = 0; x < L[0]; x++) {
+                cplx acc[3] = {0, 0, 0}, tmp[3];
+                for (int mu = 0; mu < 3; mu++) {
+                    int xs, ys, zs;
+                    shifted(L, x, y, z, mu, 1, &xs, &ys, &zs);
+                    matvec(link(L, U, x, y, z, t, mu), in + site3(L, xs, ys, zs) * 3, tmp);
+                    for (int a = 0; a < 3; a++) acc[a] += tmp[a];
+                    shifted(L, x, y, z, mu, -1, &xs, &ys, &zs);
+                    matvec_dag(link(L, U, xs, ys, zs, t, mu), in + site3(L, xs, ys, zs) * 3, tmp);
+                    for (int a = 0; a < 3; a++) acc[a] += tmp[a];
+                }
+                cplx *o = out + site3(L, x, y, z) * 3;
+                for (int a = 0; a < 3; a++) o[a] = acc[a];
+            }
+}
+
+/*
+ * One-link 3D Laplacian of Sec. 2 (lattice spacing 1), nabla^2 = H - 6:
+ *   (nabla^2 psi)(x) = sum_mu [ U_mu(x) psi(x+mu^) - 2 psi(x) + U_mu^dag(x-mu^) psi(x-mu^) ],
+ * written out per direction, independently of or_hop_onelink.
+ */
+void or_lap_onelink(const int L[4], const cplx *U, int t, const cplx *in, cplx *out)
+{
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < L[2]; z++)
+        for (int y = 0; y < L[1]; y++)
+            for (int x = 0; x < L[0]; x++) {
+                const cplx *c = in + site3(L, x, y, z) * 3;
+                cplx acc[3] = {0, 0, 0};
+                for (int mu = 0; mu < 3; mu++) {
+                    int xf, yf, zf, xb, yb, zb;
+                    cplx f[3], b[3];
+                    shifted(L, x, y, z, mu, 1, &xf, &yf, &zf);
+                    shifted(L, x, y, z, mu, -1, &xb, &yb, &zb);
+                    matvec(link(L, U, x, y, z, t, mu), in + site3(L, xf, yf, zf) * 3, f);
+                    matvec_dag(link(L, U, xb, yb, zb, t, mu), in + site3(L, xb, yb, zb) * 3, b);
+                    for (int a = 0; a < 3; a++) acc[a] += f[a] - 2.0 * c[a] + b[a];
+                }
+                cplx *o = out + site3(L, x, y, z) * 3;
+                for (int a = 0; a < 3; a++) o[a] = acc[a];
+            }
+}
+
+/*
+ * Gaussian smearing in the hopping form (eq. gsmear without its constant C):
+ *   psi <- (1 + alpha H)^n psi, as n repetitions of psi <- psi + alpha H psi.
+ */
+void or_gsmear_hop(const int L[4], const cplx *U, int t, int n, double alpha, cplx *psi)
+{
+    long V3 = (long)L[0] * L[1] * L[2];
+    cplx *h = malloc(sizeof(cplx) * 3 * V3);
+    for (int k = 0; k < n; k++) {
+        or_hop_onelink(L, U, t, psi, h);
+        for (long i = 0; i < 3 * V3; i++)
+            psi[i] += alpha * h[i];
+    }
+    free(h);
+}
+
+/*
+ * One-link smearing in the Laplacian form of Sec. 2 with the width parameter of
+ * eq. tlSmear:  psi <- (1 + (sigma/n) nabla^2)^n psi, n literal repetitions.
+ * By the identity that follows eq. gsmear, (1 + alpha H)^n = (1 + 6 alpha)^n
+ * (1 + alpha' nabla^2)^n with alpha' = alpha / (1 + 6 alpha), i.e. sigma = n alpha'.
+ */
+void or_smear_onelink(const int L[4], const cplx *U, int t, int n, double sigma, cplx *psi)
+{
+    long V3 = (long)L[0] * L[1] * L[2];
+    cplx *lap = malloc(sizeof(cplx) * 3 * V3);
+    double step = sigma / (double)n;
+    for (int k = 0; k < n; k++) {
+        or_lap_onelink(L, U, t, psi, lap);
+        for (long i = 0; i < 3 * V3; i++)
+            psi[i] += step * lap[i];
+    }
+    free(lap);
+}
+
+void or_smear_onelink_batch(const int L[4], const cplx *U, int n_rhs, const int *t_of_rhs,
+                            int n, double sigma, cplx *psi)
+{
+    long V3 = (long)L[0] * L[1] * L[2];
+    for (int r = 0; r < n_rhs; r++)
+        or_smear_onelink(L, U, t_of_rhs[r], n, sigma, psi + (long)r * 3 * V3);
 }
 
 /* sum_x |psi(x)|^2 over n_sites colour vectors, plain sequential FP64 sum. */

@@ -283,6 +283,93 @@ def pin_smear_batch(orc):
         assert np.abs(out[r] - orc.smear(W, t, 5, 1.0, psi[r])).max() == 0.0
 
 
+# ------------------------------------------------------------- one-link smearing (Sec. 2)
+
+def pin_onelink_plane_waves(orc):
+    """Unit links: exp(i p.x) e_c is an eigenvector of H with eigenvalue 2 sum_mu cos p_mu and
+    of nabla^2 = H - 6 with eigenvalue -4 sum_mu sin^2(p_mu / 2).  At L_mu = 1, 2 the two
+    neighbours coincide and both hops count."""
+    for L3 in ((4, 6, 8), (5, 3, 7), (1, 2, 3)):
+        Lx, Ly, Lz = L3
+        U = synth.unit_gauge(L3 + (1,))
+        z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing='ij')
+        for k in ((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 2, 3), (Lx - 1, 1, Lz // 2)):
+            k = (k[0] % Lx, k[1] % Ly, k[2] % Lz)
+            phase = np.exp(2j * np.pi * (k[0] * x / Lx + k[1] * y / Ly + k[2] * z / Lz))
+            psi = np.zeros((Lz, Ly, Lx, 3), np.complex128)
+            psi[..., 1] = phase
+            lam_h = 2.0 * sum(np.cos(2 * np.pi * k[i] / L3[i]) for i in range(3))
+            assert np.abs(orc.hop_onelink(U, 0, psi) - lam_h * psi).max() < TOL
+            lam = checks.plane_wave_eigenvalue_onelink(k, L3)
+            assert np.abs(orc.laplacian_onelink(U, 0, psi) - lam * psi).max() < TOL
+
+
+def pin_onelink_dense(orc):
+    """Dense 4x4x3 matrices with SU(3) links: nabla^2 Hermitian with spectrum in [-12, 0],
+    and H = nabla^2 + 6 entry by entry (two independent code paths)."""
+    L = (4, 4, 3, 1)
+    U = _haar_links(L, 70)
+    D = checks.dense_operator(lambda v: orc.laplacian_onelink(U, 0, v), (3, 4, 4, 3))
+    Hm = checks.dense_operator(lambda v: orc.hop_onelink(U, 0, v), (3, 4, 4, 3))
+    assert np.abs(D - D.conj().T).max() < TOL
+    ev = np.linalg.eigvalsh(D)
+    assert ev.min() >= -12.0 - 1e-12 and ev.max() <= 1e-12
+    assert np.abs(Hm - (D + 6.0 * np.eye(D.shape[0]))).max() < TOL
+
+
+def pin_onelink_covariance_and_slice(orc):
+    """nabla^2[U^G](G psi) = G nabla^2[U](psi); the result on slice t reads only the spatial
+    links of slice t."""
+    L = (4, 5, 6, 2)
+    U = _haar_links(L, 71)
+    G = synth.gauge_transform(L, 72)
+    UG = H.transform_links(U, G)
+    for t in range(L[3]):
+        psi = synth.random_field(_rng(73 + t), (L[2], L[1], L[0], 3))
+        a = orc.laplacian_onelink(UG, t, H.transform_vector(psi, G[t]))
+        b = H.transform_vector(orc.laplacian_onelink(U, t, psi), G[t])
+        assert checks.max_rel(a, b) < TOL
+    U2 = U.copy()
+    U2[0] = synth.gauge_field(L, "haar", 74)[0]
+    U2[..., 3, :, :] = np.eye(3)
+    psi = synth.random_field(_rng(75), (L[2], L[1], L[0], 3))
+    assert np.abs(orc.laplacian_onelink(U, 1, psi) - orc.laplacian_onelink(U2, 1, psi)).max() == 0.0
+
+
+def pin_gsmear_identity(orc):
+    """The rewriting that follows eq. gsmear: (1 + alpha H)^n = (1 + 6 alpha)^n (1 + alpha' nabla^2)^n
+    with alpha' = alpha / (1 + 6 alpha), i.e. the Laplacian-form smearing with sigma = n alpha'.
+    Also sigma = 0 is the identity and n = 1 is psi + sigma nabla^2 psi."""
+    L = (6, 5, 4, 2)
+    U = _haar_links(L, 76)
+    psi = synth.random_field(_rng(77), (L[2], L[1], L[0], 3))
+    for alpha, n in ((0.05, 7), (0.1, 12), (-0.02, 5)):
+        a = orc.gsmear_hop(U, 1, n, alpha, psi)
+        ap = alpha / (1.0 + 6.0 * alpha)
+        b = (1.0 + 6.0 * alpha) ** n * orc.smear_onelink(U, 1, n, n * ap, psi)
+        assert checks.max_rel(a, b) < 1e-12
+    assert np.abs(orc.smear_onelink(U, 0, 9, 0.0, psi) - psi).max() == 0.0
+    one = orc.smear_onelink(U, 0, 1, 0.13, psi)
+    assert checks.max_rel(one, psi + 0.13 * orc.laplacian_onelink(U, 0, psi)) < TOL
+    ts = [1, 0, 1]
+    batch = np.stack([psi, 2 * psi, 1j * psi])
+    out = orc.smear_onelink_batch(U, ts, 4, 0.3, batch)
+    for r in range(3):
+        assert np.abs(out[r] - orc.smear_onelink(U, ts[r], 4, 0.3, batch[r])).max() == 0.0
+
+
+def pin_onelink_free_field(orc):
+    """Unit links: a smeared point source equals the plane-wave closed form."""
+    L3 = (8, 6, 10)
+    U = synth.unit_gauge(L3 + (1,))
+    for c, x0 in ((0, (0, 0, 0)), (2, (1, 2, 3))):
+        psi = synth.point_source(L3, c, x0)
+        out = orc.smear_onelink(U, 0, 12, 1.5, psi)
+        ref = np.zeros_like(out)
+        ref[..., c] = checks.free_kernel_onelink_dft(L3, 12, 1.5, x0)
+        assert np.abs(out - ref).max() < TOL
+
+
 # ------------------------------------------------------------- reductions
 
 def pin_reductions(orc):

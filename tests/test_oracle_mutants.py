@@ -33,6 +33,16 @@ MUTANTS = {
     "smear step sigma": ("double step = sigma / (double)n;", "double step = sigma;"),
     "smear one step short": ("for (int k = 0; k < n; k++) {\n        or_lap_twolink", "for (int k = 1; k < n; k++) {\n        or_lap_twolink"),
     "smear wrong slice": ("or_smear(L, W, t_of_rhs[r], n, sigma", "or_smear(L, W, 0, n, sigma"),
+    "onelink hop two sites": ("shifted(L, x, y, z, mu, 1, &xs, &ys, &zs);\n                    matvec(link(",
+                              "shifted(L, x, y, z, mu, 2, &xs, &ys, &zs);\n                    matvec(link("),
+    "onelink hop forward link at neighbour": ("matvec(link(L, U, x, y, z, t, mu), in + site3(L, xs, ys, zs) * 3, tmp);",
+                                              "matvec(link(L, U, xs, ys, zs, t, mu), in + site3(L, xs, ys, zs) * 3, tmp);"),
+    "onelink laplacian centre -1": ("acc[a] += f[a] - 2.0 * c[a] + b[a];", "acc[a] += f[a] - 1.0 * c[a] + b[a];"),
+    "onelink laplacian backward no dagger": ("matvec_dag(link(L, U, xb, yb, zb, t, mu)", "matvec(link(L, U, xb, yb, zb, t, mu)"),
+    "onelink laplacian backward link at x": ("matvec_dag(link(L, U, xb, yb, zb, t, mu)", "matvec_dag(link(L, U, x, y, z, t, mu)"),
+    "gsmear alpha sign": ("psi[i] += alpha * h[i];", "psi[i] -= alpha * h[i];"),
+    "onelink smear one step short": ("for (int k = 0; k < n; k++) {\n        or_lap_onelink",
+                                     "for (int k = 1; k < n; k++) {\n        or_lap_onelink"),
     "norm drops imaginary": ("s += creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);", "s += creal(psi[i]) * creal(psi[i]);"),
     "dot conjugates second": ("s += conj(phi[i]) * psi[i];", "s += phi[i] * conj(psi[i]);"),
     "site norm no sqrt": ("out[i] = sqrt(s);", "out[i] = s;"),
