@@ -54,6 +54,15 @@
  *   matrix having modulus <= 1).  Colour vectors keep the format of the
  *   precision.  A field built with TL_W12 must be used with TL_W12 and the
  *   same precision.
+ * - One-link Gaussian smearing (Sec. 2, eq. gsmear and the rewriting that
+ *   follows it): a `prec` carrying TL_ONELINK names a field of the links
+ *   U_mu(x) themselves, packed by tl_pack_links in the same layout (and size)
+ *   as a two-link field, and makes tl_laplacian apply the one-link Laplacian
+ *   nabla^2 = H - 6 (hops of one site, no 1/4) and tl_smear / tl_plan_create
+ *   apply (1 + (sigma/n) nabla^2)^n with 0 <= sigma/n <= 1/6.  The hopping
+ *   form C (1 + alpha H)^n of eq. gsmear equals C (1 + 6 alpha)^n times this
+ *   with sigma = n alpha / (1 + 6 alpha).  Only the step variants 0 and 4 run
+ *   one-link fields (the autotuner restricts itself to them).
  */
 #ifndef TWOLINK_H
 #define TWOLINK_H
@@ -78,7 +87,8 @@ enum {
 };
 
 enum { TL_F64 = 0, TL_F32 = 1, TL_F16S = 2, TL_BF16 = 3 };
-enum { TL_W12 = 16 };   /* OR into a precision: twelve-real (two-row) two-link storage */
+enum { TL_W12 = 16 };   /* OR into a precision: twelve-real (two-row) link storage */
+enum { TL_ONELINK = 32 };  /* OR into a precision: a one-link field and the one-link operators */
 
 /* tl_smear / tl_plan_create flags */
 enum {
@@ -181,13 +191,25 @@ int tl_build_twolinks(tl_ctx *ctx, const tl_geom *g, const void *U,
                       const int32_t *slices, int n_slices, int prec, void *W);
 
 /*
+ * One-link field for one-link Gaussian smearing (Sec. 2): the spatial links
+ * U_mu(x), mu = x, y, z, of the listed slices, rounded to precision `prec`,
+ * which must carry TL_ONELINK (and may carry TL_W12).  Arguments, layout and
+ * size as for tl_build_twolinks; TL_ERR_PRECISION without TL_ONELINK (and
+ * tl_build_twolinks refuses TL_ONELINK).
+ */
+int tl_pack_links(tl_ctx *ctx, const tl_geom *g, const void *U,
+                  const int32_t *slices, int n_slices, int prec, void *W);
+
+/*
  * One application of the two-link Laplacian of eq. tlLapl1 (including the
  * factor 1/4 and the -6 term) on time slice t:  out = Lap in.
  *   W, w_slices, n_w_slices  as in tl_job; t must be one of W's slices
  *   in, out  device complex128 [Lz][Ly][Lx][3]; out must not overlap in
  * `in` is rounded to the storage precision first; the arithmetic is FP64 for
  * TL_F64 and FP32 otherwise; the result is rounded to the storage precision
- * and then widened to complex128.  Uses context scratch memory.
+ * and then widened to complex128.  Uses context scratch memory.  With
+ * TL_ONELINK in prec (W from tl_pack_links): the one-link Laplacian
+ * nabla^2 = H - 6 of Sec. 2 instead.
  */
 int tl_laplacian(tl_ctx *ctx, const tl_geom *g, const void *W, const int32_t *w_slices,
                  int n_w_slices, int prec, int t, const void *in, void *out);

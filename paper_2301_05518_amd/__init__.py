@@ -16,7 +16,10 @@ Layouts (torch tensors on the context's device):
 
 Precisions: "f64", "f32", "f16s", "bf16" (colour vectors and two-links), each
 also as "<prec>-w12": two-links stored as their first two rows only (12 reals),
-the third rebuilt in the kernels, valid for SU(3) gauge links only.
+the third rebuilt in the kernels, valid for SU(3) gauge links only.  A suffix
+"-onelink" (after "-w12" if both) selects one-link Gaussian smearing (Sec. 2):
+the field then comes from Context.pack_links and the operators hop one site
+(nabla^2 = H - 6, 0 <= sigma/n <= 1/6).
 """
 from __future__ import annotations
 
@@ -25,9 +28,9 @@ from dataclasses import dataclass
 from typing import Sequence
 
 from . import _lib
-from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_PLAIN, TL_W12, TwolinkError  # noqa: F401
+from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_ONELINK, TL_PLAIN, TL_W12, TwolinkError  # noqa: F401
 
-__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE", "TL_W12",
+__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE", "TL_W12", "TL_ONELINK",
            "twolinks_bytes", "library"]
 
 
@@ -149,6 +152,13 @@ class Context:
     # -- the path
     def build_twolinks(self, L, U, prec="f32", slices=None, W=None):
         """Two-link field W_mu(x) = U_mu(x) U_mu(x+mu^) (FP64 math, stored in prec)."""
+        return self._links(self.lib.tl_build_twolinks, L, U, prec, slices, W)
+
+    def pack_links(self, L, U, prec="f32-onelink", slices=None, W=None):
+        """One-link field U_mu(x) for one-link smearing (prec must end in "-onelink")."""
+        return self._links(self.lib.tl_pack_links, L, U, prec, slices, W)
+
+    def _links(self, fn, L, U, prec, slices, W):
         import torch
         n = int(L[3]) if slices is None else len(slices)
         nbytes = twolinks_bytes(L, prec, n)
@@ -157,9 +167,8 @@ class Context:
             W = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self._torch_device())
         _need(W, "uint8", nbytes, "W", at_least=True)
         arr, ns = _i32(slices)
-        self._check(self.lib.tl_build_twolinks(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(U)),
-                                               arr, ns if slices is not None else 0, _prec(prec),
-                                               ctypes.c_void_p(_ptr(W))))
+        self._check(fn(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(U)),
+                       arr, ns if slices is not None else 0, _prec(prec), ctypes.c_void_p(_ptr(W))))
         W._tl_prec = _prec(prec)
         return W
 

@@ -11,16 +11,19 @@ ERRORS = {
     -1: "TL_ERR_ARG", -2: "TL_ERR_SHAPE", -3: "TL_ERR_PRECISION", -4: "TL_ERR_DEVICE",
     -5: "TL_ERR_HIP", -6: "TL_ERR_NOMEM", -7: "TL_ERR_UNSUPPORTED",
 }
-TL_W12 = 16   # OR into a precision: twelve-real (two-row) two-link storage
-PREC = {"f64": 0, "f32": 1, "f16s": 2, "bf16": 3,
-        "f64-w12": 0 | TL_W12, "f32-w12": 1 | TL_W12, "f16s-w12": 2 | TL_W12, "bf16-w12": 3 | TL_W12}
+TL_W12 = 16       # OR into a precision: twelve-real (two-row) link storage
+TL_ONELINK = 32   # OR into a precision: a one-link field and the one-link operators
+_BASE = {"f64": 0, "f32": 1, "f16s": 2, "bf16": 3}
+# "<prec>[-w12][-onelink]"
+PREC = {b + w + o: v | (TL_W12 if w else 0) | (TL_ONELINK if o else 0)
+        for b, v in _BASE.items() for w in ("", "-w12") for o in ("", "-onelink")}
 TL_PLAIN, TL_GRAPH, TL_AUTOTUNE = 1, 2, 4
 TL_NORM2, TL_DOT, TL_SITE_NORM = 0, 1, 2
 
 # every symbol the header declares
 EXPORTS = [
     "tl_version", "tl_create", "tl_destroy", "tl_set_stream", "tl_sync", "tl_last_error",
-    "tl_check_geom", "tl_twolinks_bytes", "tl_build_twolinks", "tl_laplacian", "tl_smear",
+    "tl_check_geom", "tl_twolinks_bytes", "tl_build_twolinks", "tl_pack_links", "tl_laplacian", "tl_smear",
     "tl_plan_create", "tl_plan_load", "tl_plan_run", "tl_plan_store", "tl_plan_reduce",
     "tl_plan_time", "tl_plan_get_info", "tl_plan_destroy", "tl_reduce",
 ]
@@ -79,6 +82,7 @@ def load() -> ctypes.CDLL:
         "tl_check_geom": (i32, [pg]),
         "tl_twolinks_bytes": (ctypes.c_size_t, [pg, i32, i32]),
         "tl_build_twolinks": (i32, [vp, pg, vp, pi32, i32, i32, vp]),
+        "tl_pack_links": (i32, [vp, pg, vp, pi32, i32, i32, vp]),
         "tl_laplacian": (i32, [vp, pg, vp, pi32, i32, i32, i32, vp, vp]),
         "tl_smear": (i32, [vp, pj, i32, i32, dbl, i32, ctypes.c_uint]),
         "tl_plan_create": (i32, [vp, pj, i32, i32, dbl, i32, ctypes.c_uint, ctypes.POINTER(vp)]),

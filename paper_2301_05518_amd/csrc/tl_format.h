@@ -108,7 +108,8 @@ __device__ __forceinline__ V ldg(const char* p) {
   return *(const __attribute__((address_space(1))) V*)p;
 }
 
-template <int P> struct Fmt;
+// Codes with the ONE bit store their (one-)link field exactly like code & 7.
+template <int P> struct Fmt : Fmt<P & 7> {};
 
 // ------------------------------------------------------------------ FP64
 template <> struct Fmt<F64> {
@@ -366,7 +367,7 @@ template <> struct Fmt<BF16 | W12> : Fmt<BF16> {
 // completes it (the third row of a twelve-real form) can be placed after a
 // barrier; for the eighteen-real forms finish_w does nothing.
 
-template <int P> struct Planes;
+template <int P> struct Planes : Planes<P & 7> {};
 
 template <class D, int NW_>
 struct FullW {

@@ -10,18 +10,23 @@ namespace tl {
 // Storage precisions (same values as TL_F64 ... TL_BF16 in twolink.h).
 enum Prec : int { F64 = 0, F32 = 1, F16S = 2, BF16 = 3 };
 
-// Format codes: a precision, or precision | W12 for the twelve-real two-link
-// form (first two rows stored, third rebuilt).  Kernels are templated on the
-// format code; colour vectors always use the format of vprec(code).
+// Format codes: a precision, | W12 for the twelve-real link form (first two
+// rows stored, third rebuilt), | ONE for a field of one-links U_mu(x) (the
+// one-link Laplacian, hops of one site) instead of two-links W_mu(x) (hops
+// of two sites).  Kernels are templated on the format code; colour vectors
+// always use the format of vprec(code), link storage that of code & 7.
 constexpr int W12 = 4;
+constexpr int ONE = 8;
 constexpr int vprec(int code) { return code & 3; }
 constexpr bool is_w12(int code) { return (code & W12) != 0; }
+constexpr bool is_one(int code) { return (code & ONE) != 0; }
+constexpr int hop_of(int code) { return is_one(code) ? 1 : 2; }
 
-// Packed two-link field: per slot, per direction mu, per site, kWBytes[code]
+// Packed link field: per slot, per direction mu, per site, kWBytes[code]
 // bytes split into planes of vector words (see tl_format.h).  Packed colour
 // vectors: per right-hand side, per site, kVBytes[code] bytes, also in planes.
-constexpr int kWBytes[8] = {144, 72, 40, 36, 96, 48, 24, 24};
-constexpr int kVBytes[8] = {48, 24, 16, 12, 48, 24, 16, 12};
+constexpr int kWBytes[16] = {144, 72, 40, 36, 96, 48, 24, 24, 144, 72, 40, 36, 96, 48, 24, 24};
+constexpr int kVBytes[16] = {48, 24, 16, 12, 48, 24, 16, 12, 48, 24, 16, 12, 48, 24, 16, 12};
 
 // Plane length: sites per plane, rounded up so every plane starts 256-byte aligned.
 inline int64_t padded_sites(int64_t v3) { return (v3 + 63) / 64 * 64; }
@@ -91,9 +96,9 @@ hipError_t launch_step(int code, int width, const StepConfig& cfg, const StepGro
                        int n_groups, int tile_base, int n_tiles, const char* in, char* out,
                        double alpha, double beta, int64_t lds, hipStream_t stream);
 
-// The step kernels of one precision, both two-link forms (one translation unit each).
+// The step kernels of one precision (one translation unit each); form = code & (W12 | ONE).
 #define TL_STEP_DECL(name)                                                                              \
-  hipError_t launch_step_##name(bool w12, int width, const StepConfig& cfg, const StepGroup* groups,     \
+  hipError_t launch_step_##name(int form, int width, const StepConfig& cfg, const StepGroup* groups,     \
                                 int n_groups, int tile_base, int n_tiles, const char* in, char* out,    \
                                 double alpha, double beta, int64_t lds, hipStream_t stream);           \
   hipError_t step_attributes_##name();
@@ -103,7 +108,8 @@ TL_STEP_DECL(f16s)
 TL_STEP_DECL(bf16)
 #undef TL_STEP_DECL
 
-// W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1, in format `code`.
+// W slots slot_first .. slot_first+n-1 from slices t_first .. t_first+n-1, in format `code`:
+// two-links W_mu(x) = U_mu(x) U_mu(x+mu^), or the links U_mu(x) themselves when is_one(code).
 hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first, int slot_first, int n,
                         void* W, hipStream_t stream);
 

@@ -13,11 +13,12 @@ namespace {
 
 // ------------------------------------------------------------------ build
 
-// W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in format P.  One thread per site.
+// W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in format P; with one != 0 the links
+// U_mu(x) themselves (a one-link field).  One thread per site.
 template <int P>
 __global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __restrict__ U, int Lx, int Ly, int Lz,
                                                               int t_first, int slot_first,
-                                                              char* __restrict__ W, int64_t Vp) {
+                                                              char* __restrict__ W, int64_t Vp, int one) {
   const int slot = slot_first + (int)blockIdx.y;
   const int t = t_first + (int)blockIdx.y;
   const int64_t V3 = (int64_t)Lx * Ly * Lz;
@@ -39,9 +40,18 @@ __global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __re
     double2 a[9], b[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) a[k] = A[k];
+    double c[18];
+    if (one) {
+#pragma unroll
+      for (int k = 0; k < 9; k++) {
+        c[2 * k] = a[k].x;
+        c[2 * k + 1] = a[k].y;
+      }
+      Fmt<P>::store_w(W + ((int64_t)slot * 3 + mu) * Vp * WB, Vp, i, c);
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < 9; k++) b[k] = B[k];
-    double c[18];
 #pragma unroll
     for (int r = 0; r < 3; r++)
 #pragma unroll
@@ -236,8 +246,8 @@ hipError_t launch_step(int code, int width, const StepConfig& cfg, const StepGro
   if (n_tiles <= 0) return hipSuccess;
   const int max_block = cfg.variant >= 5 ? 512 : 256;
   if (cfg.block < 64 || cfg.block > max_block || cfg.block % 64 != 0 || cfg.tz < 1) return hipErrorInvalidValue;
-  if (code < 0 || code > (BF16 | W12)) return hipErrorInvalidValue;
-  const bool w = is_w12(code);
+  if (code < 0 || code > (BF16 | W12 | ONE)) return hipErrorInvalidValue;
+  const int w = code & (W12 | ONE);
   switch (vprec(code)) {
     case F64: return launch_step_f64(w, width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
     case F32: return launch_step_f32(w, width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, stream);
@@ -254,9 +264,11 @@ hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first
   const dim3 grid((unsigned)((V3 + 255) / 256), (unsigned)n_slices);
   const double2* u = static_cast<const double2*>(U);
   char* w = static_cast<char*>(W);
+  if (code < 0 || code > (BF16 | W12 | ONE)) return hipErrorInvalidValue;
+  const int one = is_one(code) ? 1 : 0;
 #define TL_BUILD(C) \
-  case C: build_twolinks_kernel<C><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp); break;
-  switch (code) {
+  case C: build_twolinks_kernel<C><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp, one); break;
+  switch (code & 7) {
     TL_BUILD(F64)
     TL_BUILD(F32)
     TL_BUILD(F16S)

@@ -22,7 +22,8 @@ using tl::StepGroup;
 
 static_assert(TL_F64 == tl::F64 && TL_F32 == tl::F32 && TL_F16S == tl::F16S && TL_BF16 == tl::BF16,
               "precision codes");
-static_assert((TL_W12 & 3) == 0, "TL_W12 is a bit above the precision codes");
+static_assert((TL_W12 & 3) == 0 && (TL_ONELINK & 3) == 0 && TL_W12 != TL_ONELINK,
+              "TL_W12 and TL_ONELINK are bits above the precision codes");
 
 struct tl_ctx {
   int device = -1;
@@ -84,11 +85,12 @@ struct DeviceGuard {
   }
 };
 
-// Internal format code of a public precision argument (precision, optionally | TL_W12), -1 if invalid.
+// Internal format code of a public precision argument (precision, optionally | TL_W12 and
+// | TL_ONELINK), -1 if invalid.
 int fmt_code(int p) {
-  const int base = p & ~TL_W12;
+  const int base = p & ~(TL_W12 | TL_ONELINK);
   if (base < TL_F64 || base > TL_BF16) return -1;
-  return base | ((p & TL_W12) ? tl::W12 : 0);
+  return base | ((p & TL_W12) ? tl::W12 : 0) | ((p & TL_ONELINK) ? tl::ONE : 0);
 }
 
 bool valid_prec(int p) { return fmt_code(p) >= 0; }
@@ -177,12 +179,18 @@ int check_wslices(tl_ctx* c, const tl_geom& g, const int32_t* w_slices, int n_w)
   return TL_OK;
 }
 
-// Coefficients of one smearing step: out = alpha in + beta sum_hops.
-void step_coeffs(int n_steps, double sigma, double* alpha, double* beta) {
+// Coefficients of one smearing step, out = alpha in + beta sum_hops:
+//   two-link (eq. tlSmear with eq. tlLapl1): in + (s/4)(sum_hops - 6 in), s = sigma/n
+//   one-link (Sec. 2, nabla^2 = H - 6):      in + s (sum_hops - 6 in)
+void step_coeffs(bool one, int n_steps, double sigma, double* alpha, double* beta) {
   const double s = sigma / (double)n_steps;
-  *alpha = 1.0 - 1.5 * s;
-  *beta = 0.25 * s;
+  const double q = one ? s : 0.25 * s;
+  *alpha = 1.0 - 6.0 * q;
+  *beta = q;
 }
+
+// Largest sigma/n for which every step factor lies in [-1, 1] (a contraction for unitary links).
+double max_step(bool one) { return one ? 1.0 / 6.0 : 2.0 / 3.0; }
 
 }  // namespace
 
@@ -292,6 +300,8 @@ int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<Step
 }
 
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
+  if (tl::is_one(p->prec) && cfg.variant != 0 && cfg.variant != 4)
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "one-link smearing runs the step variants 0 and 4 only");
   if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1)
     return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernels take FP64 groups of one RHS only");
   std::vector<StepGroup> gs;
@@ -370,6 +380,7 @@ int plan_autotune(tl_plan* p) {
   const int cu = std::max(c->n_cu, 1);
   for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
     const bool lds_variant = variant >= 5;
+    if (tl::is_one(p->prec) && variant != 0 && variant != 4) continue;   // one-link: hops of one site
     if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && p->width > 1) continue;   // would run variant 0
     if (lds_variant && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
@@ -605,11 +616,18 @@ size_t tl_twolinks_bytes(const tl_geom* g, int prec, int n_slices) {
   return (size_t)n_slices * 3 * (size_t)tl::padded_sites(vol3(*g)) * tl::kWBytes[fmt_code(prec)];
 }
 
-int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
-                      void* W) {
+namespace {
+
+// Shared by tl_build_twolinks (two-links, no TL_ONELINK bit) and tl_pack_links (one-links,
+// TL_ONELINK bit required).
+int build_links(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
+                void* W, bool one) {
   if (!c) return TL_ERR_ARG;
   TL_TRY(check_geom(c, g));
   if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+  if (tl::is_one(fmt_code(prec)) != one)
+    return fail(c, TL_ERR_PRECISION, one ? "tl_pack_links needs TL_ONELINK in prec"
+                                         : "TL_ONELINK fields are built by tl_pack_links");
   if (!U || !W) return fail(c, TL_ERR_ARG, "U and W must be non-NULL device pointers");
   if (!slices) {
     if (n_slices != 0 && n_slices != g->L[3])
@@ -638,6 +656,18 @@ int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t*
     j = k;
   }
   return TL_OK;
+}
+
+}  // namespace
+
+int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
+                      void* W) {
+  return build_links(c, g, U, slices, n_slices, prec, W, false);
+}
+
+int tl_pack_links(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
+                  void* W) {
+  return build_links(c, g, U, slices, n_slices, prec, W, true);
 }
 
 int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_slices, int n_w_slices, int prec,
@@ -684,7 +714,9 @@ int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_sl
   char* A = s + 1024;
   char* B = A + fb;
   TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(vp, in, A, offdev, 1, V3, Vp, c->stream); }));
-  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(code, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, -1.5, 0.25,
+  // Lap = alpha in + beta sum_hops: two-link -3/2, 1/4 (eq. tlLapl1); one-link -6, 1 (H - 6)
+  const double la = tl::is_one(code) ? -6.0 : -1.5, lb = tl::is_one(code) ? 1.0 : 0.25;
+  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(code, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, la, lb,
                                       0, c->stream); }));
   return launch(c, "unpack", [&] { return tl::launch_unpack(vp, B, out, offdev, 1, V3, Vp, c->stream); });
 }
@@ -700,9 +732,11 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
   if ((flags & TL_PLAIN) && (flags & TL_GRAPH)) return fail(c, TL_ERR_ARG, "TL_PLAIN runs eager launches; it excludes TL_GRAPH");
   if (n_steps < 0) return fail(c, TL_ERR_ARG, "n_steps = %d is negative", n_steps);
   if (!std::isfinite(sigma)) return fail(c, TL_ERR_ARG, "sigma is not finite");
+  const bool one = tl::is_one(fmt_code(prec));
   if (n_steps > 0) {
     const double s = sigma / n_steps;
-    if (s < 0.0 || s > 2.0 / 3.0) return fail(c, TL_ERR_ARG, "sigma/n = %g outside [0, 2/3]", s);
+    if (s < 0.0 || s > max_step(one))
+      return fail(c, TL_ERR_ARG, "sigma/n = %g outside [0, %s]", s, one ? "1/6" : "2/3");
   }
   for (int j = 0; j < n_jobs; j++) {
     const tl_job& jb = jobs[j];
@@ -724,7 +758,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
   p->n_steps = n_steps;
   p->sigma = sigma;
   p->flags = flags;
-  if (n_steps > 0) step_coeffs(n_steps, sigma, &p->alpha, &p->beta);
+  if (n_steps > 0) step_coeffs(one, n_steps, sigma, &p->alpha, &p->beta);
   const int max_width = (flags & TL_PLAIN) ? 1 : 4;
 
   // resident order: per job, per slot (in slice order), RHS in job order;

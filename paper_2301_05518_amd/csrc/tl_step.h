@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
+  constexpr int D = hop_of(P);   // hop distance: 2 (two-link field), 1 (one-link field)
   constexpr int VB = kVBytes[P];
   (void)VB;
   const TileSweep sw = xcd_sweep(n_tiles, rev);
@@ -139,8 +140,8 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
     const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
     if (xy >= LxLy) continue;
     const int y = xy / Lx, x = xy - y * Lx;
-    const int xyp[2] = {y * Lx + wrap_step(x, 2, Lx), wrap_step(y, 2, Ly) * Lx + x};    // +2 in x, y
-    const int xym[2] = {y * Lx + wrap_step(x, -2, Lx), wrap_step(y, -2, Ly) * Lx + x};  // -2 in x, y
+    const int xyp[2] = {y * Lx + wrap_step(x, D, Lx), wrap_step(y, D, Ly) * Lx + x};    // +D in x, y
+    const int xym[2] = {y * Lx + wrap_step(x, -D, Lx), wrap_step(y, -D, Ly) * Lx + x};  // -D in x, y
     const char* Wmu[3] = {g.W, g.W + g.w_mu_stride, g.W + 2 * g.w_mu_stride};
     const int nr = g.nr;
     // Slots r >= nr of a narrower group read RHS nr-1 and store nothing: every load
@@ -157,8 +158,8 @@ __global__ __launch_bounds__(256) void step_direct(const StepGroup* __restrict__
     const int z1 = min(z0 + tz, Lz);
     for (int z = z0; z < z1; z++) {
       const int64_t zo = (int64_t)z * LxLy;
-      const int64_t zp = (int64_t)wrap_step(z, 2, Lz) * LxLy;
-      const int64_t zm = (int64_t)wrap_step(z, -2, Lz) * LxLy;
+      const int64_t zp = (int64_t)wrap_step(z, D, Lz) * LxLy;
+      const int64_t zm = (int64_t)wrap_step(z, -D, Lz) * LxLy;
       const int64_t site = zo + xy;
       const int64_t fwd[3] = {zo + xyp[0], zo + xyp[1], zp + xy};
       const int64_t bwd[3] = {zo + xym[0], zo + xym[1], zm + xy};
@@ -592,6 +593,7 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using F = Fmt<P>;
   using real = typename F::real;
+  constexpr int D = hop_of(P);   // hop distance: 2 (two-link field), 1 (one-link field)
   const TileSweep sw = xcd_sweep(n_tiles, rev);
   for (int m = 0; m < sw.n; m++) {
     const int tl = sw.tile(m);
@@ -606,8 +608,8 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
     const int xy = txy * (int)blockDim.x + (int)threadIdx.x;
     if (xy >= LxLy) continue;
     const int y = xy / Lx, x = xy - y * Lx;
-    const int xf = y * Lx + wrap_step(x, 2, Lx), xb = y * Lx + wrap_step(x, -2, Lx);
-    const int yf = wrap_step(y, 2, Ly) * Lx + x, yb = wrap_step(y, -2, Ly) * Lx + x;
+    const int xf = y * Lx + wrap_step(x, D, Lx), xb = y * Lx + wrap_step(x, -D, Lx);
+    const int yf = wrap_step(y, D, Ly) * Lx + x, yb = wrap_step(y, -D, Ly) * Lx + x;
     const int nr = g.nr;
     const char* pin[R];
     char* pout[R];
@@ -621,8 +623,8 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
     const int z1 = min(z0 + tz, Lz);
     for (int z = z0; z < z1; z++) {
       const int64_t zo = (int64_t)z * LxLy;
-      const int64_t zf = (int64_t)wrap_step(z, 2, Lz) * LxLy + xy;
-      const int64_t zb = (int64_t)wrap_step(z, -2, Lz) * LxLy + xy;
+      const int64_t zf = (int64_t)wrap_step(z, D, Lz) * LxLy + xy;
+      const int64_t zb = (int64_t)wrap_step(z, -D, Lz) * LxLy + xy;
       const int64_t site = zo + xy;
       real acc[R][6];
 #pragma unroll
@@ -1216,37 +1218,49 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
   // never selects it for FP64 groups wider than one RHS)
   if (cfg.variant >= 5 && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
-  const bool direct = cfg.variant == 0 || (vprec(P) == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
-                                           cfg.variant < 5);
-  (void)lds;
-  constexpr int R1 = (vprec(P) == F64 && R > 2) ? 1 : R;
-  constexpr int R2 = (vprec(P) == F64) ? 1 : R;
-  const real a = (real)alpha, b = (real)beta;
-  if (direct)
-    step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-  else if (cfg.variant == 1)
-    step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-  else if (cfg.variant == 2)
-    step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-  else if (cfg.variant == 3)
-    step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-  else if (cfg.variant == 4)
-    step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-  else if (cfg.variant == 7) {
-    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
-                                                              a, b);
-  } else if (cfg.variant == 6) {
-    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
+  if constexpr (is_one(P)) {   // one-link fields: hops of one site, variants 0 and 4 only
+    const real a = (real)alpha, b = (real)beta;
+    if (cfg.variant == 0)
+      step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 4)
+      step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else
+      return hipErrorInvalidValue;
+    (void)lds;
+    return hipGetLastError();
+  } else {   // two-link fields: every variant
+    const bool direct = cfg.variant == 0 || (vprec(P) == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
+                                             cfg.variant < 5);
+    (void)lds;
+    constexpr int R1 = (vprec(P) == F64 && R > 2) ? 1 : R;
+    constexpr int R2 = (vprec(P) == F64) ? 1 : R;
+    const real a = (real)alpha, b = (real)beta;
+    if (direct)
+      step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 1)
+      step_zmarch<P, R1, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 2)
+      step_zring<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 3)
+      step_zfront<P, R2, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 4)
+      step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
+    else if (cfg.variant == 7) {
+      if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+      step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
+                                                                a, b);
+    } else if (cfg.variant == 6) {
+      if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+      step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
+                                                                 a, b);
+    } else if (cfg.variant == 5) {
+      if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+      step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
                                                                a, b);
-  } else if (cfg.variant == 5) {
-    if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-    step_zlds<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
-                                                             a, b);
-  } else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+    } else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
 }
 
 template <int P, int R>
@@ -1285,14 +1299,19 @@ hipError_t launch_step_p(int width, const StepConfig& cfg, const StepGroup* grou
   }
 }
 
-// Both two-link forms of storage precision P.
+// Every link form of storage precision P (form = code & (W12 | ONE)).
 template <int P>
-hipError_t launch_step_both(bool w12, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
+hipError_t launch_step_both(int form, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
                             int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
                             int64_t lds, hipStream_t s) {
-  if (w12)
-    return launch_step_p<P | W12>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
-  return launch_step_p<P>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+  switch (form) {
+    case 0: return launch_step_p<P>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case W12: return launch_step_p<P | W12>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case ONE: return launch_step_p<P | ONE>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    case W12 | ONE:
+      return launch_step_p<P | W12 | ONE>(width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int P>

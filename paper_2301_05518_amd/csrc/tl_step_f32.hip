@@ -1,12 +1,12 @@
-// Smearing step kernels stored in F32: both two-link forms (18 and 12 reals).
+// Smearing step kernels stored in F32: every link form (two-links or one-links, 18 or 12 reals).
 #include "tl_step.h"
 
 namespace tl {
 
-hipError_t launch_step_f32(bool w12, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
+hipError_t launch_step_f32(int form, int width, const StepConfig& cfg, const StepGroup* groups, int n_groups,
                           int tile_base, int n_tiles, const char* in, char* out, double alpha, double beta,
                           int64_t lds, hipStream_t stream) {
-  return launch_step_both<F32>(w12, width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds,
+  return launch_step_both<F32>(form, width, cfg, groups, n_groups, tile_base, n_tiles, in, out, alpha, beta, lds,
                           stream);
 }
 

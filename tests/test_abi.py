@@ -65,7 +65,11 @@ def test_twolinks_bytes(lib):
     # twelve-real forms: two rows of 3 complex per matrix
     for p, b in {0: 96, 1: 48, 2: 24, 3: 24}.items():
         assert lib.tl_twolinks_bytes(ctypes.byref(geom(8, 8, 8, 4)), p | _lib.TL_W12, 2) == 2 * 3 * 512 * b
-    for bad in (4, 7 | _lib.TL_W12, 32, -1, _lib.TL_W12 | 8):
+    # one-link fields share the two-link layout
+    for p, b in {0: 144, 1: 72, 2: 40, 3: 36}.items():
+        for extra, bb in ((0, b), (_lib.TL_W12, {0: 96, 1: 48, 2: 24, 3: 24}[p])):
+            assert lib.tl_twolinks_bytes(ctypes.byref(geom(8, 8, 8, 4)), p | extra | _lib.TL_ONELINK, 1) == 3 * 512 * bb
+    for bad in (4, 7 | _lib.TL_W12, 64, -1, _lib.TL_W12 | 8, _lib.TL_ONELINK | 5):
         assert lib.tl_twolinks_bytes(ctypes.byref(geom(8, 8, 8, 4)), bad, 1) == 0
 
 
@@ -105,6 +109,33 @@ def test_build_validation(lib, hctx):
     assert f(hctx, ctypes.byref(g), FAKE, sl, 2, 1, FAKE) == -4            # valid: no device
     assert f(hctx, ctypes.byref(g), FAKE, None, 0, 1, FAKE) == -4
     assert b"host-only" in lib.tl_last_error(hctx)
+    # two-links and one-links have their own entry points
+    one = 1 | _lib.TL_ONELINK
+    assert f(hctx, ctypes.byref(g), FAKE, None, 0, one, FAKE) == -3
+    assert b"tl_pack_links" in lib.tl_last_error(hctx)
+    pk = lib.tl_pack_links
+    assert pk(hctx, ctypes.byref(g), FAKE, None, 0, 1, FAKE) == -3
+    assert b"TL_ONELINK" in lib.tl_last_error(hctx)
+    assert pk(hctx, ctypes.byref(bad), FAKE, None, 0, one, FAKE) == -2
+    assert pk(hctx, ctypes.byref(g), FAKE, None, 0, one | _lib.TL_W12, FAKE) == -4   # valid: no device
+
+
+def test_onelink_plan_limits(lib, hctx):
+    """One-link plans need sigma/n <= 1/6 (two-link: 2/3)."""
+    g = geom(4, 4, 4, 2)
+    ts = (ctypes.c_int32 * 1)(0)
+    jobs = (_lib.Job * 1)()
+    jobs[0].g = g
+    jobs[0].W = FAKE.value
+    jobs[0].n_rhs = 1
+    jobs[0].t_of_rhs = ts
+    jobs[0].psi = FAKE.value
+    out = ctypes.c_void_p()
+    f = lib.tl_plan_create
+    assert f(hctx, jobs, 1, 10, 2.0, 1 | _lib.TL_ONELINK, 0, ctypes.byref(out)) == -1
+    assert b"1/6" in lib.tl_last_error(hctx)
+    assert f(hctx, jobs, 1, 12, 2.0, 1 | _lib.TL_ONELINK, 0, ctypes.byref(out)) == -4
+    assert f(hctx, jobs, 1, 10, 2.0, 1, 0, ctypes.byref(out)) == -4
 
 
 def test_laplacian_validation(lib, hctx):
