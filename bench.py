@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--cpu-rhs", type=int, default=24, help="RHS in the CPU oracle sample")
     ap.add_argument("--flags", type=int, default=6, help="plan flags (2 graph | 4 autotune)")
+    ap.add_argument("--onelink", action="store_true",
+                    help="one-link Gaussian smearing (hops of one site, nabla^2 = H - 6) instead of two-link")
     ap.add_argument("--w12", action="store_true",
                     help="twelve-real two-link storage (two rows stored, third rebuilt; SU(3) links)")
     ap.add_argument("--tile", default=None, help="fixed step tiling 'variant,block,tz,grid' (no tuning)")
@@ -66,7 +68,7 @@ def kernel_source_hash() -> str:
 
 
 def workload_key(args) -> str:
-    return f"workload{args.workload}" + ("-w12" if args.w12 else "")
+    return f"workload{args.workload}" + ("-w12" if args.w12 else "") + ("-onelink" if args.onelink else "")
 
 
 def measured_traffic(workload_key: str):
@@ -139,7 +141,7 @@ def links_on_device(torch, lat, dev, workers):
     return U
 
 
-def cpu_baseline(lat, wl, U_dev, n_rhs_sample):
+def cpu_baseline(lat, wl, U_dev, n_rhs_sample, onelink=False):
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     import numpy as np
     from oracle import core
@@ -151,16 +153,19 @@ def cpu_baseline(lat, wl, U_dev, n_rhs_sample):
     updates = 0
     for t in slices:
         u = U_dev[t:t + 1].cpu().numpy()
-        Wt = orc.build_twolinks(u)
+        Wt = None if onelink else orc.build_twolinks(u)
         for r, tr in enumerate(ts):
             if tr != t:
                 continue
-            orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
+            if onelink:
+                orc.smear_onelink(u, 0, wl.n_steps, wl.sigma, lat.source(r))
+            else:
+                orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
             updates += lat.V3 * wl.n_steps
     dt = time.perf_counter() - t0
     return {"value": updates / dt, "unit": "RHS-site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(ts)} of {len(lat.t_of_rhs)} RHS ({len(slices)} slices, {lat.L[0]}^3) x {wl.n_steps} "
-                      f"steps incl. their two-link builds, FP64, {dt:.1f} s"}
+                      f"steps{'' if onelink else ' incl. their two-link builds'}, FP64, {dt:.1f} s"}
 
 
 def main():
@@ -182,7 +187,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     wl = synth.workload(args.workload)
-    prec = wl.precisions[0] + ("-w12" if args.w12 else "")
+    base = wl.precisions[0]
+    form = ("-w12" if args.w12 else "") + ("-onelink" if args.onelink else "")
+    prec = base + form
+
+    def links(lat, U, pr, slices=None, W=None):
+        """Two-link field, or the packed links for one-link smearing."""
+        fn = ctx.pack_links if pr.endswith("-onelink") else ctx.build_twolinks
+        return fn(lat.L, U, pr, slices=slices, W=W)
+
     workers = min(16, os.cpu_count() or 1)
     log(f"[bench] workload {args.workload}: {wl.name}; drawing inputs")
     t_in = time.perf_counter()
@@ -198,14 +211,14 @@ def main():
     ctx = tl.Context(0)
     jobs = []
     for lat, U, psi, slices in jobs_in:
-        W = ctx.build_twolinks(lat.L, U, prec, slices=slices)
+        W = links(lat, U, prec, slices)
         jobs.append(tl.Job(lat.L, W, lat.t_of_rhs, psi, slices))
     plan = ctx.plan(jobs, wl.n_steps, wl.sigma, prec, args.flags)
     n_rhs = sum(len(l.t_of_rhs) for l in wl.lattices)
 
     def one_pass():
         for (lat, U, _, slices), j in zip(jobs_in, jobs):
-            ctx.build_twolinks(lat.L, U, prec, slices=slices, W=j.W)
+            links(lat, U, prec, slices, j.W)
         plan.load()
         plan.run()
         norms = plan.reduce("norm2")
@@ -268,15 +281,15 @@ def main():
         ev1.synchronize()
         return ev0.elapsed_time(ev1) / reps
 
-    build_ms = timed(lambda: [ctx.build_twolinks(lat.L, U, prec, slices=s, W=j.W)
+    build_ms = timed(lambda: [links(lat, U, prec, s, j.W)
                               for (lat, U, _, s), j in zip(jobs_in, jobs)])
     pack_ms = timed(plan.load)
     unpack_ms = timed(plan.store)
     norm_ms = timed(lambda: plan.reduce("norm2"))
     smear_ms = step_ms * wl.n_steps
     lat0, U0 = jobs_in[0][0], jobs_in[0][1]
-    Wall = ctx.build_twolinks(lat0.L, U0, prec)
-    build_all_ms = timed(lambda: ctx.build_twolinks(lat0.L, U0, prec, W=Wall), reps=2)
+    Wall = links(lat0, U0, prec)
+    build_all_ms = timed(lambda: links(lat0, U0, prec, W=Wall), reps=2)
     del Wall
     torch.cuda.empty_cache()
     smear_rate = info["rhs_sites"] * wl.n_steps / (smear_ms * 1e-3)
@@ -286,9 +299,9 @@ def main():
     if not args.no_plain:
         pjobs = []
         for (lat, U, psi, slices) in jobs_in:
-            W64 = ctx.build_twolinks(lat.L, U, "f64", slices=slices)
+            W64 = links(lat, U, "f64" + form.replace("-w12", ""), slices)
             pjobs.append(tl.Job(lat.L, W64, lat.t_of_rhs, psi, slices))
-        p64 = ctx.plan(pjobs, wl.n_steps, wl.sigma, "f64", tl.TL_PLAIN)
+        p64 = ctx.plan(pjobs, wl.n_steps, wl.sigma, "f64" + form.replace("-w12", ""), tl.TL_PLAIN)
         p64.load()
         launch_ms = p64.time(reps=1)
         pinfo = p64.info()
@@ -307,8 +320,8 @@ def main():
     # tuned plan on the same resident inputs: reported beside the headline, not as `value`
     w12 = None
     if not args.w12:
-        wprec = prec + "-w12"
-        wjobs = [tl.Job(lat.L, ctx.build_twolinks(lat.L, U, wprec, slices=slices), lat.t_of_rhs, psi, slices)
+        wprec = base + "-w12" + form
+        wjobs = [tl.Job(lat.L, links(lat, U, wprec, slices), lat.t_of_rhs, psi, slices)
                  for (lat, U, psi, slices) in jobs_in]
         pw = ctx.plan(wjobs, wl.n_steps, wl.sigma, wprec, args.flags)
         pw.load()
@@ -328,7 +341,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], min(args.cpu_rhs, len(wl.lattices[0].t_of_rhs)))
+        cpu = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], min(args.cpu_rhs, len(wl.lattices[0].t_of_rhs)),
+                           args.onelink)
         log(f"[bench] oracle {cpu['value']:.3e} /s on {cpu['cores']} threads")
 
     lat = wl.lattices[0]
@@ -353,6 +367,7 @@ def main():
             "sigma": wl.sigma,
             "storage": prec,
             "accumulate": "f64" if wl.precisions[0] == "f64" else "f32",
+            "operator": "one-link Laplacian H - 6" if args.onelink else "two-link Laplacian (eq. tlLapl1)",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
             "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip", "n_tiles", "group_width")},
         },
