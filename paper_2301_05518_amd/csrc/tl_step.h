@@ -1131,6 +1131,8 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
       PL::finish_w(mxb);
       PL::finish_w(myf);
       PL::finish_w(myb);
+      // x hops of every RHS, then the y hops: per RHS the order (x fwd, x bwd, y fwd,
+      // y bwd) is unchanged, and the next plane's x two-links can be issued in between
       real acc[R][6];
 #pragma unroll
       for (int r = 0; r < R; r++) {
@@ -1143,6 +1145,16 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
 #pragma unroll
         for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + sxb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
         mdv_acc(mxb, v, acc[r]);
+      }
+      // keep the next plane's loads below the hops that free their registers
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {   // next plane: x two-links
+        PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
+        PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real v[6];
 #pragma unroll
         for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
         mv_acc(myf, v, acc[r]);
@@ -1150,11 +1162,8 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         for (int c = 0; c < 3; c++) { const c2 w = buf[(r * 3 + c) * nsite + syb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
         mdv_acc(myb, v, acc[r]);
       }
-      // keep the next plane's loads below the hops that free their registers
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (MORE) {   // next plane: in-plane two-links and halo rows
-        PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
-        PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+      if constexpr (MORE) {   // next plane: y two-links and halo rows
         PL::load_w_raw(wp[1], zno + (uint32_t)xy, myf);
         PL::load_w_raw(wp[1], zno + (uint32_t)ybw, myb);
 #pragma unroll
