@@ -1126,6 +1126,11 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
 #pragma unroll
           for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[1][r][2 * c], ring[1][r][2 * c + 1]};
       }
+      // next plane: halo rows (the registers were just written to LDS)
+      if constexpr (MORE) {
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], zno + (uint32_t)hxy, hv[r]);
+      }
       __syncthreads();
       PL::finish_w(mxf);
       PL::finish_w(mxb);
@@ -1163,11 +1168,9 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         mdv_acc(myb, v, acc[r]);
       }
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (MORE) {   // next plane: y two-links and halo rows
+      if constexpr (MORE) {   // next plane: y two-links
         PL::load_w_raw(wp[1], zno + (uint32_t)xy, myf);
         PL::load_w_raw(wp[1], zno + (uint32_t)ybw, myb);
-#pragma unroll
-        for (int r = 0; r < R; r++) PL::load_v(ip[r], zno + (uint32_t)hxy, hv[r]);
       }
       // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
       if (up) {
@@ -1183,15 +1186,10 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
           mdv_acc(wz[1], ring[2][r], acc[r]);
         }
       }
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        real o[6];
-#pragma unroll
-        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[1][r][c]);
-        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
-      }
+      // next plane: shift the ring (ring[0] then holds the current plane) and issue the colour
+      // vectors ahead of the next plane and its z two-link before the axpy and store
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (MORE) {   // next plane: colour vectors ahead of it and its z two-link
+      if constexpr (MORE) {
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
@@ -1205,6 +1203,14 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
 #pragma unroll
         for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ring[2][r]);
         PL::load_w(wp[2], up ? zno + (uint32_t)xy : (uint32_t)(wrap_sel(zn - 2, Lz) * LxLy + xy), wz[1]);
+      }
+      constexpr int cur = MORE ? 0 : 1;   // ring slot of the current plane
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real o[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[cur][r][c]);
+        if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
       }
       z = zn;
       it++;
