@@ -1126,10 +1126,13 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
 #pragma unroll
           for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[1][r][2 * c], ring[1][r][2 * c + 1]};
       }
-      // next plane: halo rows (the registers were just written to LDS)
+      // next plane: halo rows (the registers were just written to LDS); only the halo
+      // threads load them (whole waves when the rows are 64 sites long)
       if constexpr (MORE) {
+        if (halo) {
 #pragma unroll
-        for (int r = 0; r < R; r++) PL::load_v(ip[r], zno + (uint32_t)hxy, hv[r]);
+          for (int r = 0; r < R; r++) PL::load_v(ip[r], zno + (uint32_t)hxy, hv[r]);
+        }
       }
       __syncthreads();
       PL::finish_w(mxf);
