@@ -61,8 +61,8 @@
  *   nabla^2 = H - 6 (hops of one site, no 1/4) and tl_smear / tl_plan_create
  *   apply (1 + (sigma/n) nabla^2)^n with 0 <= sigma/n <= 1/6.  The hopping
  *   form C (1 + alpha H)^n of eq. gsmear equals C (1 + 6 alpha)^n times this
- *   with sigma = n alpha / (1 + 6 alpha).  Only the step variants 0 and 4 run
- *   one-link fields (the autotuner restricts itself to them).
+ *   with sigma = n alpha / (1 + 6 alpha).  Only the step variants 0, 4 and 7
+ *   run one-link fields (the autotuner restricts itself to them).
  */
 #ifndef TWOLINK_H
 #define TWOLINK_H

@@ -274,8 +274,8 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
       s.rows = 0;
       s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
     }
-    if (cfg.variant >= 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd
-      const int chains = (g.L[2] & 1) ? 1 : 2;
+    if (cfg.variant >= 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd (and for
+      const int chains = (tl::is_one(p->prec) || (g.L[2] & 1)) ? 1 : 2;   // one-links: consecutive planes)
       const int clen = g.L[2] / chains;
       s.n_z_tiles = chains * ((clen + cfg.tz - 1) / cfg.tz);
     } else {
@@ -300,8 +300,8 @@ int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<Step
 }
 
 int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
-  if (tl::is_one(p->prec) && cfg.variant != 0 && cfg.variant != 4)
-    return fail(p->ctx, TL_ERR_UNSUPPORTED, "one-link smearing runs the step variants 0 and 4 only");
+  if (tl::is_one(p->prec) && cfg.variant != 0 && cfg.variant != 4 && cfg.variant != 7)
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "one-link smearing runs the step variants 0, 4 and 7 only");
   if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1)
     return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernels take FP64 groups of one RHS only");
   std::vector<StepGroup> gs;
@@ -380,7 +380,7 @@ int plan_autotune(tl_plan* p) {
   const int cu = std::max(c->n_cu, 1);
   for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
     const bool lds_variant = variant >= 5;
-    if (tl::is_one(p->prec) && variant != 0 && variant != 4) continue;   // one-link: hops of one site
+    if (tl::is_one(p->prec) && variant != 0 && variant != 4 && variant != 7) continue;   // one-link: hops of one site
     if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && p->width > 1) continue;   // would run variant 0
     if (lds_variant && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}

@@ -1018,7 +1018,9 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
 // two-links and halo rows (into the registers those hops just freed), and after
 // its store the next plane's colour vectors ahead in the march and its z
 // two-link (into the ring slots the z hops just freed).  The arithmetic and its
-// order are those of variant 6.
+// order are those of variant 6.  With a one-link field (hops of one site) the
+// tile marches consecutive planes and the LDS neighbours sit one row or column
+// away (the two halo rows cover them).
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ groups, int n_groups,
                                                   int tile_base, int n_tiles, int tz, int rev,
@@ -1027,6 +1029,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
   using PL = Planes<P>;
   using real = typename Fmt<P>::real;
   using c2 = typename Complex2<real>::type;
+  constexpr int D = hop_of(P);   // hop distance: 2 (two-links), 1 (one-links: one chain of consecutive planes)
   extern __shared__ __align__(16) unsigned char lds_raw[];
   c2* const lds = reinterpret_cast<c2*>(lds_raw);
   const TileSweep sw = xcd_sweep(n_tiles, rev);
@@ -1040,7 +1043,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const int local = tile - g.tile_begin;
     const int tzi = local / g.n_xy_tiles;          // chain chunk index: n_z_tiles = chains * chunks
     const int y0 = (local - tzi * g.n_xy_tiles) * rows;
-    const int chains = (Lz & 1) ? 1 : 2;
+    const int chains = (D == 2 && !(Lz & 1)) ? 2 : 1;
     const int clen = Lz / chains;                  // planes per chain
     const int chunks = (clen + tz - 1) / tz;
     const int chain = tzi / chunks, chunk = tzi - chain * chunks;
@@ -1051,12 +1054,12 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const int row = active ? trow : 0;
     const int y = y0 + row;
     const int xy = y * Lx + x;
-    const int xbw = y * Lx + wrap_sel(x - 2, Lx);
-    const int ybw = wrap_sel(y - 2, Ly) * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - D, Lx);
+    const int ybw = wrap_sel(y - D, Ly) * Lx + x;
     const int nsite = (rows + 4) * Lx;
     const int own = (row + 2) * Lx + x;
-    const int sxf = (row + 2) * Lx + wrap_sel(x + 2, Lx), sxb = (row + 2) * Lx + wrap_sel(x - 2, Lx);
-    const int syf = (row + 4) * Lx + x, syb = row * Lx + x;
+    const int sxf = (row + 2) * Lx + wrap_sel(x + D, Lx), sxb = (row + 2) * Lx + wrap_sel(x - D, Lx);
+    const int syf = (row + 2 + D) * Lx + x, syb = (row + 2 - D) * Lx + x;
     const bool halo = t < 4 * Lx;
     const int hr = halo ? trow : 0;
     const int hrho = hr < 2 ? hr - 2 : rows + hr - 2;
@@ -1078,10 +1081,10 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const int nz = min(k0 + tz, clen) - k0;        // planes of this chunk
     const bool up = ((chunk & 1) == 0) != (rev != 0);
     const int kf = up ? k0 : k0 + nz - 1;
-    int z = wrap_sel(chain + 2 * kf, Lz);
-    const int step = up ? 2 : -2;
+    int z = wrap_sel(chain + D * kf, Lz);
+    const int step = up ? D : -D;
     // ring[0]: plane behind in the march, ring[1]: current, ring[2]: ahead.
-    // wz[1]: the z two-link loaded for the current plane (W_z(z) marching up, W_z(z-2)
+    // wz[1]: the z link loaded for the current plane (W_z(z) marching up, W_z(z-D)
     // marching down), wz[0]: the one loaded for the previous plane.
     real ring[3][R][6];
     real wz[2][18];
@@ -1097,7 +1100,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         PL::load_v(ip[r], (uint32_t)(wrap_sel(z + step, Lz) * LxLy + xy), ring[2][r]);
         PL::load_v(ip[r], zo + hxy, hv[r]);
       }
-      const uint32_t zm = (uint32_t)(wrap_sel(z - 2, Lz) * LxLy + xy);
+      const uint32_t zm = (uint32_t)(wrap_sel(z - D, Lz) * LxLy + xy);
       PL::load_w(wp[2], up ? zm : zc, wz[0]);
       PL::load_w(wp[2], up ? zc : zm, wz[1]);
       PL::load_w_raw(wp[0], zc, mxf);
@@ -1205,7 +1208,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         const int za = wrap_sel(zn + step, Lz);
 #pragma unroll
         for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ring[2][r]);
-        PL::load_w(wp[2], up ? zno + (uint32_t)xy : (uint32_t)(wrap_sel(zn - 2, Lz) * LxLy + xy), wz[1]);
+        PL::load_w(wp[2], up ? zno + (uint32_t)xy : (uint32_t)(wrap_sel(zn - D, Lz) * LxLy + xy), wz[1]);
       }
       constexpr int cur = MORE ? 0 : 1;   // ring slot of the current plane
 #pragma unroll
@@ -1236,15 +1239,19 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
   // never selects it for FP64 groups wider than one RHS)
   if (cfg.variant >= 5 && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
-  if constexpr (is_one(P)) {   // one-link fields: hops of one site, variants 0 and 4 only
+  if constexpr (is_one(P)) {   // one-link fields: hops of one site, variants 0, 4 and 7
     const real a = (real)alpha, b = (real)beta;
     if (cfg.variant == 0)
       step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
     else if (cfg.variant == 4)
       step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-    else
+    else if (cfg.variant == 7) {
+      constexpr int R2 = (vprec(P) == F64) ? 1 : R;
+      if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+      step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev,
+                                                                in, out, a, b);
+    } else
       return hipErrorInvalidValue;
-    (void)lds;
     return hipGetLastError();
   } else {   // two-link fields: every variant
     const bool direct = cfg.variant == 0 || (vprec(P) == F64 && R > (cfg.variant == 1 ? 2 : 1) && cfg.variant != 4 &&
@@ -1292,16 +1299,25 @@ hipError_t launch_step_t(const StepConfig& cfg, const StepGroup* groups, int n_g
 
 template <int P, int R>
 hipError_t allow_lds() {
-  for (const void* f : {reinterpret_cast<const void*>(&step_zlds<P, R, false>),
-                        reinterpret_cast<const void*>(&step_zlds<P, R, true>),
-                        reinterpret_cast<const void*>(&step_zchain<P, R, false>),
-                        reinterpret_cast<const void*>(&step_zchain<P, R, true>),
-                        reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
-                        reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (e != hipSuccess) return e;
+  if constexpr (is_one(P)) {
+    for (const void* f : {reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
+                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  } else {
+    for (const void* f : {reinterpret_cast<const void*>(&step_zlds<P, R, false>),
+                          reinterpret_cast<const void*>(&step_zlds<P, R, true>),
+                          reinterpret_cast<const void*>(&step_zchain<P, R, false>),
+                          reinterpret_cast<const void*>(&step_zchain<P, R, true>),
+                          reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
+                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  return hipSuccess;
 }
 
 template <int P>
@@ -1336,12 +1352,16 @@ template <int P>
 hipError_t step_attributes_both() {
   hipError_t e = hipSuccess;
   if constexpr (P == F64) {
-    for (hipError_t r : {allow_lds<P, 1>(), allow_lds<P | W12, 1>()})
+    for (hipError_t r : {allow_lds<P, 1>(), allow_lds<P | W12, 1>(), allow_lds<P | ONE, 1>(),
+                         allow_lds<P | W12 | ONE, 1>()})
       if (r != hipSuccess) e = r;
   } else {
     for (hipError_t r : {allow_lds<P, 1>(), allow_lds<P, 2>(), allow_lds<P, 3>(), allow_lds<P, 4>(),
                          allow_lds<P | W12, 1>(), allow_lds<P | W12, 2>(), allow_lds<P | W12, 3>(),
-                         allow_lds<P | W12, 4>()})
+                         allow_lds<P | W12, 4>(), allow_lds<P | ONE, 1>(), allow_lds<P | ONE, 2>(),
+                         allow_lds<P | ONE, 3>(), allow_lds<P | ONE, 4>(), allow_lds<P | W12 | ONE, 1>(),
+                         allow_lds<P | W12 | ONE, 2>(), allow_lds<P | W12 | ONE, 3>(),
+                         allow_lds<P | W12 | ONE, 4>()})
       if (r != hipSuccess) e = r;
   }
   return e;

@@ -116,12 +116,17 @@ def test_free_field_closed_form(ctx, torch):
     assert np.abs(out - ref).max() < 1e-13
 
 
-TILES = ["0,64,1,0", "0,128,3,256", "0,256,2,0,1,1", "4,64,1,0", "4,256,3,16", "4,128,2,0,1,1", "0,64,5,7,0,1"]
+TILES = ["0,64,1,0", "0,128,3,256", "0,256,2,0,1,1", "4,64,1,0", "4,256,3,16", "4,128,2,0,1,1", "0,64,5,7,0,1",
+         "7,512,16,0", "7,256,3,0,1,1", "7,512,1,8,0,1", "7,64,4,0,1,0", "7,512,5,4,1,1"]
 
 
 @pytest.mark.parametrize("prec", PRECS + ["bf16-w12"])
 def test_variants_bit_identical_onelink(ctx, orc, torch, prec, monkeypatch):
-    cases = [((10, 6, 13, 3), [0, 2, 0, 0]), ((5, 7, 2, 1), [0, 0]), ((3, 1, 4, 2), [1])]
+    # every lattice has a full-row tiling (Ly with a divisor >= 4) for variant 7; FP64 groups
+    # of one RHS there
+    cases = [((10, 8, 13, 3), [0, 2, 0, 0]), ((5, 4, 2, 1), [0, 0]), ((3, 4, 1, 2), [1])]
+    if prec == "f64":
+        cases = [((10, 8, 13, 3), [0, 2]), ((5, 4, 2, 1), [0]), ((3, 4, 1, 2), [1])]
     lats = []
     for k, (L, ts) in enumerate(cases):
         U = haar(L, 40 + k)
@@ -150,7 +155,7 @@ def test_refusals(ctx, torch, monkeypatch):
     W1 = ctx.pack_links(L, U, "f32-onelink")
     with pytest.raises(ValueError, match="built with precision code"):
         ctx.smear([tl.Job(L, W1, [0], psi)], 2, 0.2, "f32")
-    monkeypatch.setenv("TL_TILE", "5,512,4,0")
+    monkeypatch.setenv("TL_TILE", "6,512,4,0")
     with pytest.raises(tl.TwolinkError, match="TL_ERR_UNSUPPORTED"):
         ctx.smear([tl.Job(L, W1, [0], psi)], 2, 0.2, "f32-onelink")
     monkeypatch.delenv("TL_TILE")
