@@ -54,7 +54,10 @@ def run_workload(ctx, torch, index, prec, flags, sample):
                 U[t].copy_(torch.from_numpy(u))
                 if t in keep:
                     host[t] = u
-        W = ctx.build_twolinks(lat.L, U, prec, slices=slices)
+        if prec.endswith("-onelink"):
+            W = ctx.pack_links(lat.L, U, prec, slices=slices)
+        else:
+            W = ctx.build_twolinks(lat.L, U, prec, slices=slices)
         psi = torch.from_numpy(lat.sources_array()).to(dev)
         jobs.append(tl.Job(lat.L, W, lat.t_of_rhs, psi, slices))
         lats.append((lat, host))
@@ -66,8 +69,10 @@ def run_workload(ctx, torch, index, prec, flags, sample):
     for (lat, host), job in zip(lats, jobs):
         for r in sample(len(lat.t_of_rhs)):
             t = lat.t_of_rhs[r]
-            Wt = orc.build_twolinks(host[t][None])
-            ref = orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
+            if prec.endswith("-onelink"):
+                ref = orc.smear_onelink(host[t][None], 0, wl.n_steps, wl.sigma, lat.source(r))
+            else:
+                ref = orc.smear(orc.build_twolinks(host[t][None]), 0, wl.n_steps, wl.sigma, lat.source(r))
             got = job.psi[r].cpu().numpy()
             mr, l2 = errors(got, ref)
             log(f"  {lat.L} RHS {r} (t={t}): max-rel {mr:.3e} l2-rel {l2:.3e}")
@@ -102,6 +107,12 @@ def test_workload3_w12(ctx, torch):
     """Workload 3 with twelve-real two-links (FP32 rows, third row rebuilt): 3 RHS sampled."""
     worst, n = run_workload(ctx, torch, 3, "f32-w12", 6, lambda k: [0, 11, k - 1])
     assert worst < tol("f32-w12", n)
+
+
+def test_workload3_onelink(ctx, torch):
+    """Workload 3's sources under one-link smearing (same sigma, hops of one site), FP32: 3 RHS sampled."""
+    worst, n = run_workload(ctx, torch, 3, "f32-onelink", 6, lambda k: [0, 13, k - 1])
+    assert worst < tol("f32", n)
 
 
 def test_workload4_uneven_bf16(ctx, torch):
