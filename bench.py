@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-w12", action="store_true",
+                    help="skip the twelve-real measurement (profiling runs: one step-kernel instance)")
     ap.add_argument("--cpu-rhs", type=int, default=24, help="RHS in the CPU oracle sample")
     ap.add_argument("--flags", type=int, default=6, help="plan flags (2 graph | 4 autotune)")
     ap.add_argument("--onelink", action="store_true",
@@ -105,9 +107,14 @@ def summarize_counters(fetch_dir, write_dir, workload_key, tile):
     """Per-launch HBM bytes of the step kernel from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by what the counter reads for a plain copy of COPY_BYTES."""
     out = {}
+    kernel = None
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
-        step = [float(r["Counter_Value"]) * 1024 for r in rows if "step_" in r["Kernel_Name"]]
+        # the step-kernel instance with the most dispatches (the plan the run timed)
+        names = [r["Kernel_Name"] for r in rows if "step_" in r["Kernel_Name"]]
+        if names and kernel is None:
+            kernel = max(set(names), key=names.count)
+        step = [float(r["Counter_Value"]) * 1024 for r in rows if r["Kernel_Name"] == kernel]
         copy = [float(r["Counter_Value"]) * 1024 for r in rows
                 if "copyBuffer" in r["Kernel_Name"] or "copy_kernel" in r["Kernel_Name"]]
         copy = [c for c in copy if c > 0.5 * COPY_BYTES]   # the calibration copy only
@@ -121,6 +128,7 @@ def summarize_counters(fetch_dir, write_dir, workload_key, tile):
     allrec = json.load(open(path)) if os.path.exists(path) else {}
     allrec[workload_key] = {
         "kernel_source_hash": kernel_source_hash(), "tile": tile,
+        "kernel": kernel.replace("void ", "").replace("tl::(anonymous namespace)::", "").split("(")[0],
         "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
         "counters": out,
     }
@@ -322,7 +330,7 @@ def main():
     # the same smearing with twelve-real two-links (rows 0, 1 stored, row 2 rebuilt), its own
     # tuned plan on the same resident inputs: reported beside the headline, not as `value`
     w12 = None
-    if not args.w12:
+    if not args.w12 and not args.no_w12:
         wprec = base + "-w12" + form
         wjobs = [tl.Job(lat.L, links(lat, U, wprec, slices), lat.t_of_rhs, psi, slices)
                  for (lat, U, psi, slices) in jobs_in]
