@@ -298,6 +298,9 @@ def main():
     lat0, U0 = jobs_in[0][0], jobs_in[0][1]
     Wall = links(lat0, U0, prec)
     build_all_ms = timed(lambda: links(lat0, U0, prec, W=Wall), reps=2)
+    # the build's own roofline: U's three spatial links read once (FP64), W written once
+    build_bytes = lat0.V3 * lat0.L[3] * 3 * 144 + tl.twolinks_bytes(lat0.L, prec, lat0.L[3])
+    build_gbs = build_bytes / (build_all_ms * 1e-3) / 1e9
     del Wall
     torch.cuda.empty_cache()
     smear_rate = info["rhs_sites"] * wl.n_steps / (smear_ms * 1e-3)
@@ -387,6 +390,9 @@ def main():
         "breakdown_ms": {"build": round(build_ms, 4), "pack": round(pack_ms, 4), "smear": round(smear_ms, 4),
                          "norms": round(norm_ms, 4), "unpack": round(unpack_ms, 4),
                          "build_all_slices": round(build_all_ms, 4)},
+        "build_roofline": {"bound": "hbm", "achieved": round(build_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(build_gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": build_bytes,
+                           "slices": lat0.L[3]},
         "smear_only_rate": smear_rate,
         "plain_fp64": plain,
         "twelve_real": w12,

@@ -14,7 +14,10 @@ namespace {
 // ------------------------------------------------------------------ build
 
 // W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in format P; with one != 0 the links
-// U_mu(x) themselves (a one-link field).  One thread per site.
+// U_mu(x) themselves (a one-link field).  One thread per (site, mu), mu fastest: the
+// threads of a wave read consecutive 144-byte link matrices of about 21 sites (the t links
+// between them are skipped), so a matrix's nine loads stay within lines the wave has
+// already brought into L1.
 template <int P>
 __global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __restrict__ U, int Lx, int Ly, int Lz,
                                                               int t_first, int slot_first,
@@ -22,54 +25,54 @@ __global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __re
   const int slot = slot_first + (int)blockIdx.y;
   const int t = t_first + (int)blockIdx.y;
   const int64_t V3 = (int64_t)Lx * Ly * Lz;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V3) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * V3) return;
+  const int64_t i = k / 3;
+  const int mu = (int)(k - 3 * i);
   const int x = (int)(i % Lx);
   const int y = (int)((i / Lx) % Ly);
   const int z = (int)(i / ((int64_t)Lx * Ly));
-  const int64_t nb[3] = {
-      ((int64_t)z * Ly + y) * Lx + wrap_step(x, 1, Lx),
-      ((int64_t)z * Ly + wrap_step(y, 1, Ly)) * Lx + x,
-      ((int64_t)wrap_step(z, 1, Lz) * Ly + y) * Lx + x};
+  const int64_t nb = mu == 0 ? ((int64_t)z * Ly + y) * Lx + wrap_step(x, 1, Lx)
+                   : mu == 1 ? ((int64_t)z * Ly + wrap_step(y, 1, Ly)) * Lx + x
+                             : ((int64_t)wrap_step(z, 1, Lz) * Ly + y) * Lx + x;
   const int64_t base = (int64_t)t * V3;
   constexpr int WB = kWBytes[P];
+  char* const Wm = W + ((int64_t)slot * 3 + mu) * Vp * WB;
+  const double2* A = U + ((base + i) * 4 + mu) * 9;
+  double2 a[9];
 #pragma unroll
-  for (int mu = 0; mu < 3; mu++) {
-    const double2* A = U + ((base + i) * 4 + mu) * 9;
-    const double2* B = U + ((base + nb[mu]) * 4 + mu) * 9;
-    double2 a[9], b[9];
+  for (int q = 0; q < 9; q++) a[q] = A[q];
+  double c[18];
+  if (one) {
 #pragma unroll
-    for (int k = 0; k < 9; k++) a[k] = A[k];
-    double c[18];
-    if (one) {
-#pragma unroll
-      for (int k = 0; k < 9; k++) {
-        c[2 * k] = a[k].x;
-        c[2 * k + 1] = a[k].y;
-      }
-      Fmt<P>::store_w(W + ((int64_t)slot * 3 + mu) * Vp * WB, Vp, i, c);
-      continue;
+    for (int q = 0; q < 9; q++) {
+      c[2 * q] = a[q].x;
+      c[2 * q + 1] = a[q].y;
     }
-#pragma unroll
-    for (int k = 0; k < 9; k++) b[k] = B[k];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-      for (int s = 0; s < 3; s++) {
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-          const double2 p = a[3 * r + k], q = b[3 * k + s];
-          re = fma_(p.x, q.x, re);
-          re = fma_(-p.y, q.y, re);
-          im = fma_(p.x, q.y, im);
-          im = fma_(p.y, q.x, im);
-        }
-        c[2 * (3 * r + s)] = re;
-        c[2 * (3 * r + s) + 1] = im;
-      }
-    Fmt<P>::store_w(W + ((int64_t)slot * 3 + mu) * Vp * WB, Vp, i, c);
+    Fmt<P>::store_w(Wm, Vp, i, c);
+    return;
   }
+  const double2* B = U + ((base + nb) * 4 + mu) * 9;
+  double2 b[9];
+#pragma unroll
+  for (int q = 0; q < 9; q++) b[q] = B[q];
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const double2 p = a[3 * r + q], w = b[3 * q + s];
+        re = fma_(p.x, w.x, re);
+        re = fma_(-p.y, w.y, re);
+        im = fma_(p.x, w.y, im);
+        im = fma_(p.y, w.x, im);
+      }
+      c[2 * (3 * r + s)] = re;
+      c[2 * (3 * r + s) + 1] = im;
+    }
+  Fmt<P>::store_w(Wm, Vp, i, c);
 }
 
 // ------------------------------------------------------------------ pack / unpack
@@ -261,7 +264,7 @@ hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first
   const int64_t V3 = (int64_t)L[0] * L[1] * L[2];
   const int64_t Vp = padded_sites(V3);
   if (n_slices <= 0 || V3 <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((V3 + 255) / 256), (unsigned)n_slices);
+  const dim3 grid((unsigned)((3 * V3 + 255) / 256), (unsigned)n_slices);
   const double2* u = static_cast<const double2*>(U);
   char* w = static_cast<char*>(W);
   if (code < 0 || code > (BF16 | W12 | ONE)) return hipErrorInvalidValue;
