@@ -61,8 +61,10 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the smearing step kernels (the kernel the traffic
+    counters measure); the build, pack and reduction kernels live elsewhere."""
     h = hashlib.sha256()
-    for f in ("tl_kernels.hip", "tl_step.h", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip",
+    for f in ("tl_step.h", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip",
               "tl_step_bf16.hip", "tl_format.h", "tl_internal.h"):
         with open(os.path.join(ROOT, "paper_2301_05518_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -224,11 +226,20 @@ def main():
     plan = ctx.plan(jobs, wl.n_steps, wl.sigma, prec, args.flags)
     n_rhs = sum(len(l.t_of_rhs) for l in wl.lattices)
 
-    def one_pass():
+    run_events = []   # HIP events around the smearing launches of each timed pass
+
+    def one_pass(timed=False):
         for (lat, U, _, slices), j in zip(jobs_in, jobs):
             links(lat, U, prec, slices, j.W)
         plan.load()
-        plan.run()
+        if timed:   # the library queues on torch's current stream, where these events go
+            ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ea.record()
+            plan.run()
+            eb.record()
+            run_events.append((ea, eb))
+        else:
+            plan.run()
         norms = plan.reduce("norm2")
         plan.store()
         return norms
@@ -239,7 +250,7 @@ def main():
     log("[bench] warm; timing")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        norms = one_pass()
+        norms = one_pass(timed=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -263,9 +274,14 @@ def main():
     del ca, cb
     torch.cuda.empty_cache()
 
-    # dominant kernel: the smearing step, timed with HIP events on the library's stream
+    # dominant kernel: the smearing step.  Its average launch duration comes from the HIP events
+    # around the smearing launches inside the timed passes above (the n launches of a pass
+    # replayed from the graph, gaps between them included); back-to-back replays outside the
+    # timed region are reported beside it.
     info = plan.info()
-    step_ms = plan.time(reps=3)
+    launches = max(1, info["launches_per_step"] * wl.n_steps)
+    step_ms = sum(a.elapsed_time(b) for a, b in run_events) / len(run_events) / launches
+    isolated_ms = plan.time(reps=3)
     achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
     key = workload_key(args)
     traffic = measured_traffic(key)
@@ -274,7 +290,8 @@ def main():
                 "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
                            "step_zpipe"][info["variant"]],
                 "algorithmic_bytes_per_launch": info["bytes_per_step"],
-                "avg_launch_ms": round(step_ms, 5), "copy_GBs": round(copy_gbs, 1)}
+                "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
+                "copy_GBs": round(copy_gbs, 1)}
     log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 
     # the pieces of a pass, timed alone on the same stream
