@@ -75,9 +75,9 @@ def workload_key(args) -> str:
     return f"workload{args.workload}" + ("-w12" if args.w12 else "") + ("-onelink" if args.onelink else "")
 
 
-def measured_traffic(workload_key: str):
+def measured_traffic(workload_key: str, tile: str):
     """HBM bytes per step-kernel launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (else None)."""
+    were taken on the current kernel source with the same tiling (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -85,7 +85,7 @@ def measured_traffic(workload_key: str):
         rec = json.load(open(path)).get(workload_key)
     except (ValueError, OSError):
         return None
-    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("tile") != tile:
         return None
     return rec.get("bytes_per_launch")
 
@@ -284,7 +284,8 @@ def main():
     isolated_ms = plan.time(reps=3)
     achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
     key = workload_key(args)
-    traffic = measured_traffic(key)
+    tile = ",".join(str(info[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))
+    traffic = measured_traffic(key, tile)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
