@@ -105,7 +105,7 @@ def _counter_rows(d, counter):
     return rows
 
 
-def summarize_counters(fetch_dir, write_dir, workload_key, tile):
+def summarize_counters(fetch_dir, write_dir, workload_key, tile, path=None):
     """Per-launch HBM bytes of the step kernel from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by what the counter reads for a plain copy of COPY_BYTES."""
     out = {}
@@ -119,14 +119,16 @@ def summarize_counters(fetch_dir, write_dir, workload_key, tile):
         step = [float(r["Counter_Value"]) * 1024 for r in rows if r["Kernel_Name"] == kernel]
         copy = [float(r["Counter_Value"]) * 1024 for r in rows
                 if "copyBuffer" in r["Kernel_Name"] or "copy_kernel" in r["Kernel_Name"]]
-        copy = [c for c in copy if c > 0.5 * COPY_BYTES]   # the calibration copy only
+        # the calibration copies only (FETCH_SIZE reads about half of their bytes; host-to-device
+        # copies read zero on these counters)
+        copy = [c for c in copy if c > 0.1 * COPY_BYTES]
         if not step or not copy:
             raise SystemExit(f"no step-kernel or calibration-copy dispatches with {counter} in {d}")
         scale = COPY_BYTES / (sum(copy) / len(copy))
         out[counter] = {"raw_bytes_per_launch": sum(step) / len(step), "launches": len(step),
                         "copy_raw_bytes": sum(copy) / len(copy), "scale": scale,
                         "bytes_per_launch": sum(step) / len(step) * scale}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
     allrec[workload_key] = {
         "kernel_source_hash": kernel_source_hash(), "tile": tile,
@@ -137,6 +139,7 @@ def summarize_counters(fetch_dir, write_dir, workload_key, tile):
     with open(path, "w") as fh:
         json.dump(allrec, fh, indent=1)
     print(json.dumps(allrec[workload_key], indent=1))
+    return allrec[workload_key]
 
 
 def links_on_device(torch, lat, dev, workers):
