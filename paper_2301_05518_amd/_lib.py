@@ -68,6 +68,9 @@ def load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2301_05518_amd.build` "
             "(there is no CPU fallback for the smearing path)")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so the
+    # process holds one runtime whose device and stream handles both sides share
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     pg, pj = ctypes.POINTER(Geom), ctypes.POINTER(Job)
