@@ -249,8 +249,10 @@ int tl_plan_store(tl_plan *plan);
  */
 int tl_plan_reduce(tl_plan *plan, int kind, const tl_plan *other, double *out);
 /* Average device time of one step kernel launch over `reps` back-to-back
- * runs of n_steps steps each, measured with HIP events on the context's
- * stream (blocks the host).  The resident fields are smeared further. */
+ * runs of n_steps steps each (after one untimed run that tunes and captures),
+ * measured with HIP events on the context's stream (blocks the host).  The
+ * resident fields are smeared reps + 1 more times: tl_plan_load before using
+ * results again. */
 int tl_plan_time(tl_plan *plan, int reps, double *ms_per_step);
 int tl_plan_get_info(const tl_plan *plan, tl_plan_info *info);
 int tl_plan_destroy(tl_plan *plan);

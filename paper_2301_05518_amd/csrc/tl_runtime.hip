@@ -401,8 +401,8 @@ int plan_autotune(tl_plan* p) {
     return rc;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(c, TL_ERR_HIP, "hipEventCreate failed");
   float best = 1e30f;
   StepConfig best_cfg = cands[0];
   const int reps = 10;
@@ -450,8 +450,8 @@ int plan_autotune(tl_plan* p) {
     }
   }
   (void)hipStreamSynchronize(c->stream);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(ref);
   (void)hipFree(flag_mem);
   if (rc != TL_OK) return rc;
@@ -943,9 +943,11 @@ int tl_plan_time(tl_plan* p, int reps, double* ms_per_step) {
   DeviceGuard dg(c->device);
   TL_TRY(tl_plan_run(p));   // tuning and graph capture happen outside the timed region
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(c, hipEventCreate(&e0));
-  HIP_TRY(c, hipEventCreate(&e1));
   int rc = TL_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(c, TL_ERR_HIP, "hipEventCreate failed");
+  }
   (void)hipEventRecord(e0, c->stream);
   for (int k = 0; k < reps && rc == TL_OK; k++) rc = tl_plan_run(p);
   (void)hipEventRecord(e1, c->stream);
