@@ -141,7 +141,7 @@ def test_smear_point_source_8cube(ctx, orc, torch):
     assert mr < 1e-12 and l2 < 1e-12
 
 
-MODES = {"batched": 0, "plain": 1, "graph": 2, "autotune": 4, "graph+autotune": 6}
+MODES = {"batched": 0, "plain": 1, "graph": 2, "autotune": 4, "graph+autotune": 6, "plain+autotune": 5}
 
 
 def test_smear_modes_bit_identical(ctx, orc, torch):
@@ -160,6 +160,28 @@ def test_smear_modes_bit_identical(ctx, orc, torch):
         assert mr < 1e-12 and l2 < 1e-12
     for name in MODES:
         assert np.array_equal(outs[name], outs["batched"]), name
+
+
+def test_side_stream_and_second_context(ctx, orc, torch):
+    """A context on a non-default torch stream (and a second context on the same device)
+    gives the same bits as the default-stream context; the caller orders the streams."""
+    import paper_2301_05518_amd as tl
+    L = (12, 8, 10, 2)
+    ts = [0, 1, 0]
+    U = haar(L, 23)
+    psi = synth.random_field(rng(23), (len(ts), L[2], L[1], L[0], 3))
+    ref = gpu_smear(ctx, [(L, U, ts, psi)], 6, 2.0, "f32", 6)[0]
+    side = torch.cuda.Stream()
+    c2 = tl.Context(0, stream=side)
+    try:
+        with torch.cuda.stream(side):
+            Ud, pd = to_dev(U), to_dev(psi)
+            W = c2.build_twolinks(L, Ud, "f32")
+            c2.smear([tl.Job(L, W, ts, pd)], 6, 2.0, "f32", 6)
+        side.synchronize()
+        assert np.array_equal(pd.cpu().numpy(), ref)
+    finally:
+        c2.close()
 
 
 VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "1,128,5,512", "2,64,4,0", "2,128,3,0",
