@@ -524,6 +524,29 @@ template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
       m[2 * k + 1] = bf16_to_f32(w[k] >> 16);
     }
   }
+  // Raw form: the nine packed words stay in m[0..8] (bit patterns) until finish_w
+  // widens them, so a two-link loaded a step ahead holds nine registers, not 18.
+  template <typename T>
+  static __device__ __forceinline__ void load_w_raw(const char* const (&pl)[NW], uint32_t i, T (&m)[18]) {
+    static_assert(sizeof(T) == 4, "BF16 two-links widen to FP32");
+    const v4u p0 = ldg<v4u>(pl[0] + i * 16u);
+    const v4u p1 = ldg<v4u>(pl[1] + i * 16u);
+    const uint32_t p2 = ldg<uint32_t>(pl[2] + i * 4u);
+    m[0] = __uint_as_float(p0.x); m[1] = __uint_as_float(p0.y); m[2] = __uint_as_float(p0.z);
+    m[3] = __uint_as_float(p0.w); m[4] = __uint_as_float(p1.x); m[5] = __uint_as_float(p1.y);
+    m[6] = __uint_as_float(p1.z); m[7] = __uint_as_float(p1.w); m[8] = __uint_as_float(p2);
+  }
+  // Widen in place from the last word down: word k fills m[2k] and m[2k+1], which
+  // hold no word not yet read.
+  template <typename T>
+  static __device__ __forceinline__ void finish_w(T (&m)[18]) {
+#pragma unroll
+    for (int k = 8; k >= 0; k--) {
+      const uint32_t w = __float_as_uint(m[k]);
+      m[2 * k + 1] = bf16_to_f32(w >> 16);
+      m[2 * k] = bf16_to_f32(w & 0xffffu);
+    }
+  }
   template <typename C>
   static __device__ __forceinline__ void v(C* b, int64_t Vp, C* (&pl)[NV]) {
     pl[0] = b;

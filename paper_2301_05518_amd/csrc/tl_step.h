@@ -1018,9 +1018,13 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
 // two-links and halo rows (into the registers those hops just freed), and after
 // its store the next plane's colour vectors ahead in the march and its z
 // two-link (into the ring slots the z hops just freed).  The arithmetic and its
-// order are those of variant 6.  With a one-link field (hops of one site) the
-// tile marches consecutive planes and the LDS neighbours sit one row or column
-// away (the two halo rows cover them).
+// order are those of variant 6.  Only the plane ahead is held in registers: a
+// thread's colour vectors of the current plane and of the plane behind are its
+// own slots of the two LDS buffers (the plane ahead is written to the other
+// buffer once the z hops have read the plane behind from it), which frees the
+// registers and the copies of a three-plane ring.  With a one-link field (hops
+// of one site) the tile marches consecutive planes and the LDS neighbours sit
+// one row or column away (the two halo rows cover them).
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ groups, int n_groups,
                                                   int tile_base, int n_tiles, int tz, int rev,
@@ -1083,21 +1087,26 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const int kf = up ? k0 : k0 + nz - 1;
     int z = wrap_sel(chain + D * kf, Lz);
     const int step = up ? D : -D;
-    // ring[0]: plane behind in the march, ring[1]: current, ring[2]: ahead.
-    // wz[1]: the z link loaded for the current plane (W_z(z) marching up, W_z(z-D)
-    // marching down), wz[0]: the one loaded for the previous plane.
-    real ring[3][R][6];
+    // ahd: colour vectors of the plane ahead in the march.  The current plane sits in
+    // the thread's own slots of LDS buffer it & 1, the plane behind in those of the
+    // other buffer.  wz[1]: the z link loaded for the current plane (W_z(z) marching
+    // up, W_z(z-D) marching down), wz[0]: the one loaded for the previous plane.
+    real ahd[R][6];
     real wz[2][18];
     real mxf[18], mxb[18], myf[18], myb[18];
     real hv[R][6];
+    // a workgroup with several tiles: every thread has finished reading the previous
+    // tile's LDS before the own slots of both buffers are written
+    __syncthreads();
     {
       const uint32_t zo = (uint32_t)(z * LxLy);
       const uint32_t zc = zo + xy;
+      real bh[R][6], cu[R][6];
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        PL::load_v(ip[r], (uint32_t)(wrap_sel(z - step, Lz) * LxLy + xy), ring[0][r]);
-        PL::load_v(ip[r], zc, ring[1][r]);
-        PL::load_v(ip[r], (uint32_t)(wrap_sel(z + step, Lz) * LxLy + xy), ring[2][r]);
+        PL::load_v(ip[r], (uint32_t)(wrap_sel(z - step, Lz) * LxLy + xy), bh[r]);
+        PL::load_v(ip[r], zc, cu[r]);
+        PL::load_v(ip[r], (uint32_t)(wrap_sel(z + step, Lz) * LxLy + xy), ahd[r]);
         PL::load_v(ip[r], zo + hxy, hv[r]);
       }
       const uint32_t zm = (uint32_t)(wrap_sel(z - D, Lz) * LxLy + xy);
@@ -1107,6 +1116,17 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
       PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
       PL::load_w_raw(wp[1], zc, myf);
       PL::load_w_raw(wp[1], zo + (uint32_t)ybw, myb);
+      if (active) {
+        c2* const bc = lds + (it & 1) * (R * 3) * nsite;
+        c2* const bb = lds + ((it + 1) & 1) * (R * 3) * nsite;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            bb[(r * 3 + c) * nsite + own] = c2{bh[r][2 * c], bh[r][2 * c + 1]};
+            bc[(r * 3 + c) * nsite + own] = c2{cu[r][2 * c], cu[r][2 * c + 1]};
+          }
+      }
     }
     // one plane step; MORE: a further plane follows in this chunk (the last step is
     // peeled off, so the loads for a next plane are unconditional inside the loop and
@@ -1116,18 +1136,13 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
       const uint32_t site = (uint32_t)(z * LxLy) + xy;
       const int zn = wrap_sel(z + step, Lz);        // next plane of the march
       const uint32_t zno = (uint32_t)(zn * LxLy);
-      c2* const buf = lds + (it & 1) * (R * 3) * nsite;
+      c2* const buf = lds + (it & 1) * (R * 3) * nsite;           // current plane
+      c2* const oth = lds + ((it + 1) & 1) * (R * 3) * nsite;     // own slots: the plane behind
       if (halo) {
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
           for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
-      }
-      if (active) {
-#pragma unroll
-        for (int r = 0; r < R; r++)
-#pragma unroll
-          for (int c = 0; c < 3; c++) buf[(r * 3 + c) * nsite + own] = c2{ring[1][r][2 * c], ring[1][r][2 * c + 1]};
       }
       // next plane: halo rows (the registers were just written to LDS); only the halo
       // threads load them (whole waves when the rows are 64 sites long)
@@ -1179,43 +1194,51 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         PL::load_w_raw(wp[1], zno + (uint32_t)ybw, myb);
       }
       // z forward: W_z(z) psi(z+2); z backward: W_z(z-2)^dag psi(z-2)
+      real bh[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = oth[(r * 3 + c) * nsite + own]; bh[r][2 * c] = w.x; bh[r][2 * c + 1] = w.y; }
       if (up) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          mv_acc(wz[1], ring[2][r], acc[r]);
-          mdv_acc(wz[0], ring[0][r], acc[r]);
+          mv_acc(wz[1], ahd[r], acc[r]);
+          mdv_acc(wz[0], bh[r], acc[r]);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          mv_acc(wz[0], ring[0][r], acc[r]);
-          mdv_acc(wz[1], ring[2][r], acc[r]);
+          mv_acc(wz[0], bh[r], acc[r]);
+          mdv_acc(wz[1], ahd[r], acc[r]);
         }
       }
-      // next plane: shift the ring (ring[0] then holds the current plane) and issue the colour
-      // vectors ahead of the next plane and its z two-link before the axpy and store
+      // next plane: the plane ahead becomes its current plane (own slots of the other
+      // buffer, after the plane behind was read from them); issue the colour vectors
+      // ahead of the next plane and its z two-link before the axpy and store
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (MORE) {
+        if (active) {
 #pragma unroll
-        for (int r = 0; r < R; r++)
+          for (int r = 0; r < R; r++)
 #pragma unroll
-          for (int c = 0; c < 6; c++) {
-            ring[0][r][c] = ring[1][r][c];
-            ring[1][r][c] = ring[2][r][c];
-          }
+            for (int c = 0; c < 3; c++) oth[(r * 3 + c) * nsite + own] = c2{ahd[r][2 * c], ahd[r][2 * c + 1]};
+        }
 #pragma unroll
         for (int c = 0; c < 18; c++) wz[0][c] = wz[1][c];
         const int za = wrap_sel(zn + step, Lz);
 #pragma unroll
-        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ring[2][r]);
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(za * LxLy + xy), ahd[r]);
         PL::load_w(wp[2], up ? zno + (uint32_t)xy : (uint32_t)(wrap_sel(zn - D, Lz) * LxLy + xy), wz[1]);
       }
-      constexpr int cur = MORE ? 0 : 1;   // ring slot of the current plane
 #pragma unroll
       for (int r = 0; r < R; r++) {
         real o[6];
 #pragma unroll
-        for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * ring[cur][r][c]);
+        for (int c = 0; c < 3; c++) {
+          const c2 w = buf[(r * 3 + c) * nsite + own];
+          o[2 * c] = fma_(beta, acc[r][2 * c], alpha * w.x);
+          o[2 * c + 1] = fma_(beta, acc[r][2 * c + 1], alpha * w.y);
+        }
         if (active && r < nr) PL::template store_v<real, NT>(op[r], site, o);
       }
       z = zn;
