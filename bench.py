@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--w12", action="store_true",
                     help="twelve-real two-link storage (two rows stored, third rebuilt; SU(3) links)")
     ap.add_argument("--tile", default=None, help="fixed step tiling 'variant,block,tz,grid' (no tuning)")
+    ap.add_argument("--prec", choices=("f64", "f32", "f16s", "bf16"), default=None,
+                    help="storage precision instead of the workload's first one (e.g. f16s for workload 2)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
                          "profiles/traffic.json and exit")
@@ -72,7 +74,8 @@ def kernel_source_hash() -> str:
 
 
 def workload_key(args) -> str:
-    return f"workload{args.workload}" + ("-w12" if args.w12 else "") + ("-onelink" if args.onelink else "")
+    return (f"workload{args.workload}" + (f"-{args.prec}" if args.prec else "") + ("-w12" if args.w12 else "")
+            + ("-onelink" if args.onelink else ""))
 
 
 def measured_traffic(workload_key: str, tile: str):
@@ -154,16 +157,18 @@ def links_on_device(torch, lat, dev, workers):
     return U
 
 
-def cpu_baseline(lat, wl, U_dev, n_rhs_sample, onelink=False):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
-    import numpy as np
-    from oracle import core
+def cpu_baseline(lat, wl, U_dev, n_rhs_sample, onelink=False, gpu_out=None):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload; with gpu_out (the
+    library's result for the sampled RHS from the sources, numpy) also the error of that result
+    against the oracle's, compared after the timed region."""
+    from oracle import checks, core
     orc = core.get()
     ts = lat.t_of_rhs[:n_rhs_sample]
     slices = sorted(set(ts))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     updates = 0
+    refs = {}
     for t in slices:
         u = U_dev[t:t + 1].cpu().numpy()
         Wt = None if onelink else orc.build_twolinks(u)
@@ -171,14 +176,22 @@ def cpu_baseline(lat, wl, U_dev, n_rhs_sample, onelink=False):
             if tr != t:
                 continue
             if onelink:
-                orc.smear_onelink(u, 0, wl.n_steps, wl.sigma, lat.source(r))
+                refs[r] = orc.smear_onelink(u, 0, wl.n_steps, wl.sigma, lat.source(r))
             else:
-                orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
+                refs[r] = orc.smear(Wt, 0, wl.n_steps, wl.sigma, lat.source(r))
             updates += lat.V3 * wl.n_steps
     dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "RHS-site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(ts)} of {len(lat.t_of_rhs)} RHS ({len(slices)} slices, {lat.L[0]}^3) x {wl.n_steps} "
-                      f"steps{'' if onelink else ' incl. their two-link builds'}, FP64, {dt:.1f} s"}
+    sample = (f"{len(ts)} of {len(lat.t_of_rhs)} RHS ({len(slices)} slices, {lat.L[0]}^3) x {wl.n_steps} "
+              f"steps{'' if onelink else ' incl. their two-link builds'}, FP64, {dt:.1f} s")
+    cpu = {"value": updates / dt, "unit": "RHS-site-updates/s", "cores": threads, "kind": "oracle",
+           "sample": sample}
+    acc = None
+    if gpu_out is not None:
+        mr = max(checks.max_rel(gpu_out[r], refs[r]) for r in refs)
+        l2 = max(checks.l2_rel(gpu_out[r], refs[r]) for r in refs)
+        acc = {"max_rel": mr, "l2_rel": l2, "against": "FP64 oracle",
+               "sample": f"RHS 0..{len(ts) - 1} of lattice 0 (worst over the sample), one pass from the sources"}
+    return cpu, acc
 
 
 def main():
@@ -200,7 +213,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     wl = synth.workload(args.workload)
-    base = wl.precisions[0]
+    base = args.prec or wl.precisions[0]
     form = ("-w12" if args.w12 else "") + ("-onelink" if args.onelink else "")
     prec = base + form
 
@@ -246,6 +259,15 @@ def main():
         norms = plan.reduce("norm2")
         plan.store()
         return norms
+
+    # the result of one pass from the sources, for the accuracy check against the oracle
+    # (the later passes start from the previous pass's output: same work, other values)
+    n_sample = min(args.cpu_rhs, len(wl.lattices[0].t_of_rhs))
+    first_out = None
+    if not args.no_cpu:
+        one_pass()
+        torch.cuda.synchronize()
+        first_out = jobs[0].psi[:n_sample].cpu().numpy()
 
     for _ in range(args.warmup):
         one_pass()
@@ -373,12 +395,12 @@ def main():
         torch.cuda.empty_cache()
         log(f"[bench] twelve-real two-links: step {w_ms * 1e3:.1f} us")
 
-    cpu = None
+    cpu = accuracy = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], min(args.cpu_rhs, len(wl.lattices[0].t_of_rhs)),
-                           args.onelink)
-        log(f"[bench] oracle {cpu['value']:.3e} /s on {cpu['cores']} threads")
+        cpu, accuracy = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], n_sample, args.onelink, first_out)
+        log(f"[bench] oracle {cpu['value']:.3e} /s on {cpu['cores']} threads; "
+            f"max-rel {accuracy['max_rel']:.2e} against it")
 
     lat = wl.lattices[0]
     out = {
@@ -392,7 +414,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": wl.precisions[0],
+        "dtype": base,
         "data": "synthetic",
         "config": {
             "workload": wl.name,
@@ -401,13 +423,14 @@ def main():
             "n_smear": wl.n_steps,
             "sigma": wl.sigma,
             "storage": prec,
-            "accumulate": "f64" if wl.precisions[0] == "f64" else "f32",
+            "accumulate": "f64" if base == "f64" else "f32",
             "operator": "one-link Laplacian H - 6" if args.onelink else "two-link Laplacian (eq. tlLapl1)",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
             "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip", "n_tiles", "group_width")},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
         "breakdown_ms": {"build": round(build_ms, 4), "pack": round(pack_ms, 4), "smear": round(smear_ms, 4),
                          "norms": round(norm_ms, 4), "unpack": round(unpack_ms, 4),
                          "build_all_slices": round(build_all_ms, 4)},

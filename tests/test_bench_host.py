@@ -1,4 +1,5 @@
-"""Host logic of bench.py, on the CPU: the one-GPU refusal and the counter summary."""
+"""Host logic of bench.py, on the CPU: the one-GPU refusal, the counter summary and the
+accuracy report against the oracle."""
 import csv
 import json
 import os
@@ -47,3 +48,23 @@ def test_counter_summary(tmp_path):
     assert abs(f["scale"] - 2.0) < 1e-12 and abs(w["scale"] - 1.0) < 1e-12   # small copy ignored
     assert abs(rec["bytes_per_launch"] - (300000 * 1024 * 2.0 + 150000 * 1024)) < 1e-3
     assert json.load(open(out))["workloadX"]["tile"] == "7,512,16,256,1,1"
+
+
+def test_accuracy_against_the_oracle():
+    """The accuracy field compares the library's result with the oracle's on the sampled RHS:
+    zero for the oracle's own result, the planted relative error for a scaled one."""
+    import numpy as np
+    import torch
+    from paper_2301_05518_amd import synth
+    wl = synth.workload(0)
+    lat = wl.lattices[0]
+    U = bench.links_on_device(torch, lat, torch.device("cpu"), 1)
+    _, none = bench.cpu_baseline(lat, wl, U, 1)
+    assert none is None
+    from oracle import core
+    orc = core.get()
+    ref = orc.smear(orc.build_twolinks(U[0:1].numpy()), 0, wl.n_steps, wl.sigma, lat.source(0))
+    cpu, acc = bench.cpu_baseline(lat, wl, U, 1, gpu_out=np.stack([ref]))
+    assert cpu["kind"] == "oracle" and acc["max_rel"] == 0.0 and acc["l2_rel"] == 0.0
+    _, acc = bench.cpu_baseline(lat, wl, U, 1, gpu_out=np.stack([ref * (1 + 1e-3)]))
+    assert abs(acc["max_rel"] - 1e-3) < 1e-9 and abs(acc["l2_rel"] - 1e-3) < 1e-9
