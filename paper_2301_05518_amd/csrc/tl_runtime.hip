@@ -385,7 +385,7 @@ int plan_autotune(tl_plan* p) {
     if (lds_variant && !c->big_lds) continue;
     const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
                                  : (variant >= 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
-    const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 64};
+    const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 128, 64};
     for (int block : blocks)
       for (int tz : tzs)
         for (int grid : {0, 8 * cu})
