@@ -1011,6 +1011,21 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
   }
 }
 
+// Words of a two-link that load_w_raw fills before finish_w completes it: 18 (eighteen-real
+// FP64, FP32 and F16S, the latter widened at load), 12 (twelve-real forms) or 9 (BF16, whose
+// packed words are widened by finish_w).
+constexpr int raw_words(int P) { return is_w12(P) ? 12 : ((P & 3) == BF16 ? 9 : 18); }
+
+// The value v of lane src of the wave (src in bytes: lane * 4).
+__device__ __forceinline__ float lane_get(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // Variant 7: variant 6 software-pipelined across plane steps.  The waves of a
 // workgroup meet at the LDS barrier every step, so they all wait for memory at
 // the same time unless a step's loads are issued a step early.  Each step
@@ -1055,6 +1070,12 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const int t = (int)threadIdx.x;
     const int trow = t / Lx, x = t - trow * Lx;
     const bool active = trow < rows;
+    // rows of 64 sites: a wave is one row and lane x holds W_x at x, so the backward x
+    // two-link W_x(x - D) is lane x - D's forward one, taken across lanes instead of loaded
+    // (FP32 forms and eighteen-real F16S; the other forms would spill the registers the
+    // second code path needs)
+    constexpr bool kXlane = (P & 3) == F32 || (P & 7) == F16S;
+    const bool xlane = kXlane && Lx == 64;
     const int row = active ? trow : 0;
     const int y = y0 + row;
     const int xy = y * Lx + x;
@@ -1113,7 +1134,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
       PL::load_w(wp[2], up ? zm : zc, wz[0]);
       PL::load_w(wp[2], up ? zc : zm, wz[1]);
       PL::load_w_raw(wp[0], zc, mxf);
-      PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
+      if (!xlane) PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
       PL::load_w_raw(wp[1], zc, myf);
       PL::load_w_raw(wp[1], zo + (uint32_t)ybw, myb);
       if (active) {
@@ -1153,6 +1174,11 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
         }
       }
       __syncthreads();
+      if (xlane) {   // every lane of the wave is active here
+        const int src = ((x - D) & 63) * 4;
+#pragma unroll
+        for (int c = 0; c < raw_words(P); c++) mxb[c] = lane_get(mxf[c], src);
+      }
       PL::finish_w(mxf);
       PL::finish_w(mxb);
       PL::finish_w(myf);
@@ -1176,7 +1202,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (MORE) {   // next plane: x two-links
         PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
-        PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+        if (!xlane) PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {

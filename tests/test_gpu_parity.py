@@ -223,6 +223,31 @@ def test_step_variants_bit_identical(ctx, orc, torch, prec, monkeypatch):
         assert mr < tol(prec, 7) and l2 < tol(prec, 7)
 
 
+ROW64_TILES = ["0,64,1,0", "5,512,3,0", "6,256,2,0,1", "7,512,4,0", "7,256,3,5,0,1", "7,512,2,3,1,1",
+               "7,256,16,0,1,0"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_variants_rows_of_64(ctx, orc, torch, prec, monkeypatch):
+    """Rows of 64 sites (one wave per row, the benchmark's row length): the LDS-staged
+    variants, whose FP32 form takes the backward x two-link from the neighbouring lane, give
+    the direct kernel's bits."""
+    L = (64, 8, 6, 2)
+    ts = [1] if prec == "f64" else [0, 0, 1, 0]
+    U = haar(L, 60)
+    psi = synth.random_field(rng(60), (len(ts), L[2], L[1], L[0], 3))
+    outs = {}
+    for tile in ROW64_TILES:
+        monkeypatch.setenv("TL_TILE", tile)
+        log(f"rows of 64 {prec}: tile {tile}")
+        outs[tile] = gpu_smear(ctx, [(L, U, ts, psi)], 6, 2.0, prec)[0]
+    for tile in ROW64_TILES[1:]:
+        assert np.array_equal(outs[tile], outs[ROW64_TILES[0]]), tile
+    ref = orc.smear_batch(orc.build_twolinks(U), ts, 6, 2.0, psi)
+    mr, l2 = errors(outs[ROW64_TILES[0]], ref)
+    assert mr < tol(prec, 6) and l2 < tol(prec, 6)
+
+
 def test_lds_variant_fp64_single_rhs(ctx, orc, torch, monkeypatch):
     """The LDS-staged kernel at FP64 (groups of one RHS) matches the direct kernel bit for bit;
     forcing it on a wider FP64 group is refused before any launch."""
