@@ -227,25 +227,58 @@ ROW64_TILES = ["0,64,1,0", "5,512,3,0", "6,256,2,0,1", "7,512,4,0", "7,256,3,5,0
                "7,256,16,0,1,0"]
 
 
+# (lattice, RHS slices, tilings): 256-thread tiles have no row tiling when Ly = 6
+ROW64_CASES = [((64, 8, 6, 2), [0, 0, 1, 0], ROW64_TILES),
+               ((64, 6, 5, 1), [0, 0, 0], ["0,64,1,0", "5,512,3,0", "7,512,4,0", "7,512,2,3,1,1", "7,512,5,0,0,1"])]
+
+
 @pytest.mark.parametrize("prec", PRECS)
-def test_step_variants_rows_of_64(ctx, orc, torch, prec, monkeypatch):
+@pytest.mark.parametrize("case", ROW64_CASES, ids=["64x8x6", "64x6x5"])
+def test_step_variants_rows_of_64(ctx, orc, torch, prec, case, monkeypatch):
     """Rows of 64 sites (one wave per row, the benchmark's row length): the LDS-staged
-    variants, whose FP32 form takes the backward x two-link from the neighbouring lane, give
-    the direct kernel's bits."""
-    L = (64, 8, 6, 2)
-    ts = [1] if prec == "f64" else [0, 0, 1, 0]
+    variants, whose FP32 and F16S forms take the backward x two-link from the neighbouring
+    lane, give the direct kernel's bits.  Ly = 6 leaves two idle waves in a 512-thread tile
+    (they still take part in the lane exchange); Lz = 5 makes a single chain."""
+    L, ts, tiles = case
+    if prec == "f64":   # the LDS-staged FP64 kernels take groups of one RHS
+        ts = [L[3] - 1]
     U = haar(L, 60)
     psi = synth.random_field(rng(60), (len(ts), L[2], L[1], L[0], 3))
     outs = {}
-    for tile in ROW64_TILES:
+    for tile in tiles:
         monkeypatch.setenv("TL_TILE", tile)
-        log(f"rows of 64 {prec}: tile {tile}")
+        log(f"rows of 64 {prec} {L}: tile {tile}")
         outs[tile] = gpu_smear(ctx, [(L, U, ts, psi)], 6, 2.0, prec)[0]
-    for tile in ROW64_TILES[1:]:
-        assert np.array_equal(outs[tile], outs[ROW64_TILES[0]]), tile
+    for tile in tiles[1:]:
+        assert np.array_equal(outs[tile], outs[tiles[0]]), tile
     ref = orc.smear_batch(orc.build_twolinks(U), ts, 6, 2.0, psi)
-    mr, l2 = errors(outs[ROW64_TILES[0]], ref)
+    mr, l2 = errors(outs[tiles[0]], ref)
     assert mr < tol(prec, 6) and l2 < tol(prec, 6)
+
+
+@pytest.mark.parametrize("prec", ["f32-onelink", "f16s-onelink", "f32-w12-onelink"])
+def test_onelink_rows_of_64(ctx, orc, torch, prec, monkeypatch):
+    """One-link fields on rows of 64 sites: the pipelined variant takes the backward x link
+    from the lane one to the left and gives the direct kernel's bits."""
+    import paper_2301_05518_amd as tl
+    L = (64, 6, 7, 2)
+    ts = [0, 0, 1]
+    U = haar(L, 61)
+    psi = synth.random_field(rng(61), (len(ts), L[2], L[1], L[0], 3))
+    outs = {}
+    for tile in ("0,64,1,0", "7,512,4,0", "7,512,3,5,0,1", "7,512,2,0,1,1"):
+        monkeypatch.setenv("TL_TILE", tile)
+        log(f"one-link rows of 64 {prec}: tile {tile}")
+        jobs = [tl.Job(L, ctx.pack_links(L, to_dev(U), prec), ts, to_dev(psi))]
+        ctx.smear(jobs, 5, 0.5, prec)
+        torch.cuda.synchronize()
+        outs[tile] = jobs[0].psi.cpu().numpy()
+    for tile, o in outs.items():
+        assert np.array_equal(o, outs["0,64,1,0"]), tile
+    ref = orc.smear_onelink_batch(U, ts, 5, 0.5, psi)
+    base = prec.replace("-onelink", "")
+    mr, l2 = errors(outs["0,64,1,0"], ref)
+    assert mr < tol(base, 5) and l2 < tol(base, 5)
 
 
 def test_lds_variant_fp64_single_rhs(ctx, orc, torch, monkeypatch):
