@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -62,14 +63,29 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources that define the smearing step kernels (the kernel the traffic
-    counters measure); the build, pack and reduction kernels live elsewhere."""
+STEP_SOURCES = ("tl_step.h", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip", "tl_step_bf16.hip",
+                "tl_format.h", "tl_internal.h")
+
+
+def code_of(text: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed: what the compiler
+    sees (these files hold no string literal containing a comment marker)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the code (comments and layout aside) of the sources that define the smearing
+    step kernels, the kernel the traffic counters measure; the build, pack and reduction
+    kernels live elsewhere.  read(name) returns a file's text (default: the working tree)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(ROOT, "paper_2301_05518_amd", "csrc", name)) as fh:
+                return fh.read()
     h = hashlib.sha256()
-    for f in ("tl_step.h", "tl_step_f64.hip", "tl_step_f32.hip", "tl_step_f16s.hip",
-              "tl_step_bf16.hip", "tl_format.h", "tl_internal.h"):
-        with open(os.path.join(ROOT, "paper_2301_05518_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in STEP_SOURCES:
+        h.update(code_of(read(f)).encode())
     return h.hexdigest()[:16]
 
 

@@ -1030,16 +1030,18 @@ __device__ __forceinline__ double lane_get(double v, int src) {
 // workgroup meet at the LDS barrier every step, so they all wait for memory at
 // the same time unless a step's loads are issued a step early.  Each step
 // therefore issues, right after its in-plane hops, the next plane's in-plane
-// two-links and halo rows (into the registers those hops just freed), and after
-// its store the next plane's colour vectors ahead in the march and its z
-// two-link (into the ring slots the z hops just freed).  The arithmetic and its
-// order are those of variant 6.  Only the plane ahead is held in registers: a
-// thread's colour vectors of the current plane and of the plane behind are its
-// own slots of the two LDS buffers (the plane ahead is written to the other
-// buffer once the z hops have read the plane behind from it), which frees the
-// registers and the copies of a three-plane ring.  With a one-link field (hops
-// of one site) the tile marches consecutive planes and the LDS neighbours sit
-// one row or column away (the two halo rows cover them).
+// two-links and halo rows (into the registers those hops just freed), and right
+// after its z hops the next plane's colour vectors ahead in the march and its z
+// two-link (into the registers the z hops just freed), before the axpy and store.
+// The arithmetic and its order are those of variant 6.  Only the plane ahead is
+// held in registers: a thread's colour vectors of the current plane and of the
+// plane behind are its own slots of the two LDS buffers (the plane ahead is
+// written to the other buffer once the z hops have read the plane behind from
+// it), which frees the registers and the copies of a three-plane ring.  On rows
+// of 64 sites a wave is one row, and the backward x two-link is taken from the
+// neighbouring lane instead of loaded.  With a one-link field (hops of one site)
+// the tile marches consecutive planes and the LDS neighbours sit one row or
+// column away (the two halo rows cover them).
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ groups, int n_groups,
                                                   int tile_base, int n_tiles, int tz, int rev,
