@@ -68,3 +68,14 @@ def test_accuracy_against_the_oracle():
     assert cpu["kind"] == "oracle" and acc["max_rel"] == 0.0 and acc["l2_rel"] == 0.0
     _, acc = bench.cpu_baseline(lat, wl, U, 1, gpu_out=np.stack([ref * (1 + 1e-3)]))
     assert abs(acc["max_rel"] - 1e-3) < 1e-9 and abs(acc["l2_rel"] - 1e-3) < 1e-9
+
+
+def test_source_hash_ignores_comments_only():
+    """The traffic record stays valid across comment and layout edits and not across code edits."""
+    assert bench.code_of("int a; // note\n/* block\n comment */  int   b;\n") == "int a; int b;"
+    files = {n: f"// {n}\nint f_{len(n)}(int x) {{ return x; }}\n" for n in bench.STEP_SOURCES}
+    h0 = bench.kernel_source_hash(files.__getitem__)
+    files["tl_step.h"] = files["tl_step.h"].replace("// tl_step.h", "/* reworded */")
+    assert bench.kernel_source_hash(files.__getitem__) == h0
+    files["tl_step.h"] = files["tl_step.h"].replace("return x;", "return x + 1;")
+    assert bench.kernel_source_hash(files.__getitem__) != h0
