@@ -82,7 +82,7 @@ enum {
     TL_ERR_PRECISION = -3,   /* unknown storage precision */
     TL_ERR_DEVICE = -4,      /* no such device, or device work on a host-only context */
     TL_ERR_HIP = -5,         /* a HIP runtime call failed (message from the runtime) */
-    TL_ERR_NOMEM = -6,       /* a library-internal device allocation failed */
+    TL_ERR_NOMEM = -6,       /* a library-internal allocation (device or host) failed */
     TL_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
 };
 

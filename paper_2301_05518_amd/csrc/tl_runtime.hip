@@ -59,6 +59,16 @@ int fail(tl_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
+// No C++ exception may cross the C interface: an entry point whose host-side bookkeeping
+// throws (in practice a failed host allocation) reports TL_ERR_NOMEM instead.
+int host_failure(tl_ctx* c) noexcept {
+  try {
+    if (c) c->err = "host allocation failed"; else g_create_err = "host allocation failed";
+  } catch (...) {
+  }
+  return TL_ERR_NOMEM;
+}
+
 #define HIP_TRY(ctx, expr)                                                                     \
   do {                                                                                         \
     hipError_t e_ = (expr);                                                                    \
@@ -84,6 +94,12 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// Makes the context's device current for the rest of the enclosing entry point, or fails
+// the call (nothing queued) when the runtime refuses to switch to it.
+#define TL_ON_DEVICE(c)                                                                  \
+  DeviceGuard dg_((c)->device);                                                          \
+  if (!dg_.ok) return fail((c), TL_ERR_DEVICE, "hipSetDevice(%d) failed", (c)->device)
 
 // Internal format code of a public precision argument (precision, optionally | TL_W12 and
 // | TL_ONELINK), -1 if invalid.
@@ -535,80 +551,110 @@ extern "C" {
 int tl_version(void) { return 10100; }
 
 int tl_create(tl_ctx** out, int device, void* stream) {
-  if (!out) return fail(nullptr, TL_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  tl_ctx* c = new (std::nothrow) tl_ctx();
-  if (!c) return fail(nullptr, TL_ERR_NOMEM, "host allocation failed");
-  const char* lg = getenv("TL_LOG");
-  c->log = lg && lg[0] == '1';
-  const char* fl = getenv("TL_FAULT");
-  if (fl) {
-    c->fault_alloc = strcmp(fl, "alloc") == 0;
-    c->fault_launch = strcmp(fl, "launch") == 0;
-  }
-  if (device == -1) {
-    c->device = -1;
+  tl_ctx* c = nullptr;
+  try {
+    if (!out) return fail(nullptr, TL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    c = new (std::nothrow) tl_ctx();
+    if (!c) return fail(nullptr, TL_ERR_NOMEM, "host allocation failed");
+    const char* lg = getenv("TL_LOG");
+    c->log = lg && lg[0] == '1';
+    const char* fl = getenv("TL_FAULT");
+    if (fl) {
+      c->fault_alloc = strcmp(fl, "alloc") == 0;
+      c->fault_launch = strcmp(fl, "launch") == 0;
+    }
+    if (device == -1) {
+      c->device = -1;
+      *out = c;
+      return TL_OK;
+    }
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+      delete c;
+      c = nullptr;
+      return fail(nullptr, TL_ERR_DEVICE, "device %d not available (%d devices%s%s)", device, e == hipSuccess ? n : 0,
+                  e == hipSuccess ? "" : ": ", e == hipSuccess ? "" : hipGetErrorString(e));
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+      delete c;
+      c = nullptr;
+      return fail(nullptr, TL_ERR_DEVICE, "hipGetDeviceProperties(%d) failed", device);
+    }
+    {
+      // the LDS-staged step kernels need more than the default dynamic-LDS limit;
+      // without it their tilings are simply not offered
+      DeviceGuard dg(device);
+      if (!dg.ok) {
+        delete c;
+        c = nullptr;
+        return fail(nullptr, TL_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+      }
+      c->big_lds = tl::init_kernel_attributes() == hipSuccess;
+      (void)hipGetLastError();
+    }
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     *out = c;
     return TL_OK;
-  }
-  int n = 0;
-  hipError_t e = hipGetDeviceCount(&n);
-  if (e != hipSuccess || device < 0 || device >= n) {
+  } catch (...) {   // a half-built context is released; *out stays NULL
+    if (out) *out = nullptr;
     delete c;
-    return fail(nullptr, TL_ERR_DEVICE, "device %d not available (%d devices%s%s)", device, e == hipSuccess ? n : 0,
-                e == hipSuccess ? "" : ": ", e == hipSuccess ? "" : hipGetErrorString(e));
+    return host_failure(nullptr);
   }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    delete c;
-    return fail(nullptr, TL_ERR_DEVICE, "hipGetDeviceProperties(%d) failed", device);
-  }
-  {
-    // the LDS-staged step kernels need more than the default dynamic-LDS limit;
-    // without it their tilings are simply not offered
-    DeviceGuard dg(device);
-    c->big_lds = tl::init_kernel_attributes() == hipSuccess;
-    (void)hipGetLastError();
-  }
-  c->device = device;
-  c->stream = static_cast<hipStream_t>(stream);
-  c->n_cu = prop.multiProcessorCount;
-  c->arch = prop.gcnArchName;
-  *out = c;
-  return TL_OK;
 }
 
 int tl_destroy(tl_ctx* c) {
-  if (!c) return TL_ERR_ARG;
-  if (c->device >= 0) {
-    DeviceGuard dg(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    if (c->scratch) (void)hipFree(c->scratch);
+  try {
+    if (!c) return TL_ERR_ARG;
+    if (c->device >= 0) {
+      DeviceGuard dg(c->device);   // teardown goes on even if the switch fails
+      (void)hipStreamSynchronize(c->stream);
+      if (c->scratch) (void)hipFree(c->scratch);
+    }
+    delete c;
+    return TL_OK;
+  } catch (...) {
+    return host_failure(nullptr);
   }
-  delete c;
-  return TL_OK;
 }
 
 int tl_set_stream(tl_ctx* c, void* stream) {
-  if (!c) return TL_ERR_ARG;
-  c->stream = static_cast<hipStream_t>(stream);
-  return TL_OK;
+  try {
+    if (!c) return TL_ERR_ARG;
+    c->stream = static_cast<hipStream_t>(stream);
+    return TL_OK;
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 int tl_sync(tl_ctx* c) {
-  if (!c) return TL_ERR_ARG;
-  TL_TRY(need_device(c));
-  DeviceGuard dg(c->device);
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  HIP_TRY(c, hipGetLastError());
-  return TL_OK;
+  try {
+    if (!c) return TL_ERR_ARG;
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipGetLastError());
+    return TL_OK;
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 const char* tl_last_error(const tl_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 int tl_check_geom(const tl_geom* g) {
-  tl_ctx tmp;
-  return check_geom(&tmp, g);
+  try {
+    tl_ctx tmp;
+    return check_geom(&tmp, g);
+  } catch (...) {
+    return host_failure(nullptr);
+  }
 }
 
 size_t tl_twolinks_bytes(const tl_geom* g, int prec, int n_slices) {
@@ -644,7 +690,7 @@ int build_links(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slice
     }
   }
   TL_TRY(need_device(c));
-  DeviceGuard dg(c->device);
+  TL_ON_DEVICE(c);
   const int code = fmt_code(prec);
   if (!slices) return launch(c, "two-link build", [&] { return tl::launch_build(code, U, g->L, 0, 0, n_slices, W, c->stream); });
   // runs of consecutive slices share a launch
@@ -662,355 +708,407 @@ int build_links(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slice
 
 int tl_build_twolinks(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
                       void* W) {
-  return build_links(c, g, U, slices, n_slices, prec, W, false);
+  try {
+    return build_links(c, g, U, slices, n_slices, prec, W, false);
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 int tl_pack_links(tl_ctx* c, const tl_geom* g, const void* U, const int32_t* slices, int n_slices, int prec,
                   void* W) {
-  return build_links(c, g, U, slices, n_slices, prec, W, true);
+  try {
+    return build_links(c, g, U, slices, n_slices, prec, W, true);
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 int tl_laplacian(tl_ctx* c, const tl_geom* g, const void* W, const int32_t* w_slices, int n_w_slices, int prec,
                  int t, const void* in, void* out) {
-  if (!c) return TL_ERR_ARG;
-  TL_TRY(check_geom(c, g));
-  if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
-  if (!W || !in || !out) return fail(c, TL_ERR_ARG, "W, in and out must be non-NULL device pointers");
-  TL_TRY(check_wslices(c, *g, w_slices, n_w_slices));
-  const int slot = slot_of(*g, w_slices, n_w_slices, t);
-  if (slot < 0) return fail(c, TL_ERR_SHAPE, "slice t = %d is not in the two-link field", t);
-  const int64_t V3 = vol3(*g), Vp = tl::padded_sites(V3);
-  const size_t nat_bytes = (size_t)V3 * 48;
-  const char* a = static_cast<const char*>(in);
-  const char* b = static_cast<const char*>(out);
-  if (a < b + nat_bytes && b < a + nat_bytes) return fail(c, TL_ERR_ARG, "in and out overlap");
-  TL_TRY(need_device(c));
-  DeviceGuard dg(c->device);
-  const int code = fmt_code(prec), vp = tl::vprec(code);
-  const size_t fb = align256((size_t)Vp * tl::kVBytes[vp]);
-  char* s = nullptr;
-  TL_TRY(ctx_scratch(c, 1024 + 2 * fb, &s));
-  StepGroup sg{};
-  StepConfig cfg{0, 256, 4, 0, 0};
-  sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[code];
-  sg.w_mu_stride = Vp * tl::kWBytes[code];
-  sg.psi_off = 0;
-  sg.rhs_stride = 0;
-  sg.Lx = g->L[0];
-  sg.Ly = g->L[1];
-  sg.Lz = g->L[2];
-  sg.Vp = (int32_t)Vp;
-  sg.nr = 1;
-  sg.n_xy_tiles = (int32_t)(((int64_t)g->L[0] * g->L[1] + cfg.block - 1) / cfg.block);
-  sg.n_z_tiles = (g->L[2] + cfg.tz - 1) / cfg.tz;
-  sg.tile_begin = 0;
-  struct {
-    StepGroup g;
-    int64_t off0;
-  } tab{sg, 0};
-  TL_TRY(upload(c, s, &tab, sizeof tab));
-  const StepGroup* gdev = reinterpret_cast<const StepGroup*>(s);
-  const int64_t* offdev = reinterpret_cast<const int64_t*>(s + offsetof(decltype(tab), off0));
-  char* A = s + 1024;
-  char* B = A + fb;
-  TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(vp, in, A, offdev, 1, V3, Vp, c->stream); }));
-  // Lap = alpha in + beta sum_hops: two-link -3/2, 1/4 (eq. tlLapl1); one-link -6, 1 (H - 6)
-  const double la = tl::is_one(code) ? -6.0 : -1.5, lb = tl::is_one(code) ? 1.0 : 0.25;
-  TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(code, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, la, lb,
-                                      0, c->stream); }));
-  return launch(c, "unpack", [&] { return tl::launch_unpack(vp, B, out, offdev, 1, V3, Vp, c->stream); });
+  try {
+    if (!c) return TL_ERR_ARG;
+    TL_TRY(check_geom(c, g));
+    if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+    if (!W || !in || !out) return fail(c, TL_ERR_ARG, "W, in and out must be non-NULL device pointers");
+    TL_TRY(check_wslices(c, *g, w_slices, n_w_slices));
+    const int slot = slot_of(*g, w_slices, n_w_slices, t);
+    if (slot < 0) return fail(c, TL_ERR_SHAPE, "slice t = %d is not in the two-link field", t);
+    const int64_t V3 = vol3(*g), Vp = tl::padded_sites(V3);
+    const size_t nat_bytes = (size_t)V3 * 48;
+    const char* a = static_cast<const char*>(in);
+    const char* b = static_cast<const char*>(out);
+    if (a < b + nat_bytes && b < a + nat_bytes) return fail(c, TL_ERR_ARG, "in and out overlap");
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+    const int code = fmt_code(prec), vp = tl::vprec(code);
+    const size_t fb = align256((size_t)Vp * tl::kVBytes[vp]);
+    char* s = nullptr;
+    TL_TRY(ctx_scratch(c, 1024 + 2 * fb, &s));
+    StepGroup sg{};
+    StepConfig cfg{0, 256, 4, 0, 0};
+    sg.W = static_cast<const char*>(W) + (int64_t)slot * 3 * Vp * tl::kWBytes[code];
+    sg.w_mu_stride = Vp * tl::kWBytes[code];
+    sg.psi_off = 0;
+    sg.rhs_stride = 0;
+    sg.Lx = g->L[0];
+    sg.Ly = g->L[1];
+    sg.Lz = g->L[2];
+    sg.Vp = (int32_t)Vp;
+    sg.nr = 1;
+    sg.n_xy_tiles = (int32_t)(((int64_t)g->L[0] * g->L[1] + cfg.block - 1) / cfg.block);
+    sg.n_z_tiles = (g->L[2] + cfg.tz - 1) / cfg.tz;
+    sg.tile_begin = 0;
+    struct {
+      StepGroup g;
+      int64_t off0;
+    } tab{sg, 0};
+    TL_TRY(upload(c, s, &tab, sizeof tab));
+    const StepGroup* gdev = reinterpret_cast<const StepGroup*>(s);
+    const int64_t* offdev = reinterpret_cast<const int64_t*>(s + offsetof(decltype(tab), off0));
+    char* A = s + 1024;
+    char* B = A + fb;
+    TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(vp, in, A, offdev, 1, V3, Vp, c->stream); }));
+    // Lap = alpha in + beta sum_hops: two-link -3/2, 1/4 (eq. tlLapl1); one-link -6, 1 (H - 6)
+    const double la = tl::is_one(code) ? -6.0 : -1.5, lb = tl::is_one(code) ? 1.0 : 0.25;
+    TL_TRY(launch(c, "laplacian", [&] { return tl::launch_step(code, 1, cfg, gdev, 1, 0, sg.n_xy_tiles * sg.n_z_tiles, A, B, la, lb,
+                                        0, c->stream); }));
+    return launch(c, "unpack", [&] { return tl::launch_unpack(vp, B, out, offdev, 1, V3, Vp, c->stream); });
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags,
                    tl_plan** out) {
-  if (!c) return TL_ERR_ARG;
-  if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (!jobs || n_jobs < 1) return fail(c, TL_ERR_ARG, "need at least one job");
-  if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
-  if (flags & ~(unsigned)(TL_PLAIN | TL_GRAPH | TL_AUTOTUNE)) return fail(c, TL_ERR_ARG, "unknown flag bits 0x%x", flags);
-  if ((flags & TL_PLAIN) && (flags & TL_GRAPH)) return fail(c, TL_ERR_ARG, "TL_PLAIN runs eager launches; it excludes TL_GRAPH");
-  if (n_steps < 0) return fail(c, TL_ERR_ARG, "n_steps = %d is negative", n_steps);
-  if (!std::isfinite(sigma)) return fail(c, TL_ERR_ARG, "sigma is not finite");
-  const bool one = tl::is_one(fmt_code(prec));
-  if (n_steps > 0) {
-    const double s = sigma / n_steps;
-    if (s < 0.0 || s > max_step(one))
-      return fail(c, TL_ERR_ARG, "sigma/n = %g outside [0, %s]", s, one ? "1/6" : "2/3");
-  }
-  for (int j = 0; j < n_jobs; j++) {
-    const tl_job& jb = jobs[j];
-    TL_TRY(check_geom(c, &jb.g));
-    if (!jb.W || !jb.psi) return fail(c, TL_ERR_ARG, "job %d: W and psi must be non-NULL", j);
-    if (jb.n_rhs < 1 || !jb.t_of_rhs) return fail(c, TL_ERR_ARG, "job %d: needs n_rhs >= 1 and t_of_rhs", j);
-    TL_TRY(check_wslices(c, jb.g, jb.w_slices, jb.n_w_slices));
-    for (int r = 0; r < jb.n_rhs; r++)
-      if (slot_of(jb.g, jb.w_slices, jb.n_w_slices, jb.t_of_rhs[r]) < 0)
-        return fail(c, TL_ERR_SHAPE, "job %d RHS %d: slice %d not in the two-link field", j, r, jb.t_of_rhs[r]);
-  }
-  TL_TRY(need_device(c));
-  DeviceGuard dg(c->device);
-
-  tl_plan* p = new (std::nothrow) tl_plan();
-  if (!p) return fail(c, TL_ERR_NOMEM, "host allocation failed");
-  p->ctx = c;
-  p->prec = fmt_code(prec);
-  p->n_steps = n_steps;
-  p->sigma = sigma;
-  p->flags = flags;
-  if (n_steps > 0) step_coeffs(one, n_steps, sigma, &p->alpha, &p->beta);
-  const int max_width = (flags & TL_PLAIN) ? 1 : 4;
-
-  // resident order: per job, per slot (in slice order), RHS in job order;
-  // groups of up to max_width RHS, balanced within a slot.
-  size_t off = 0;
-  for (int j = 0; j < n_jobs; j++) {
-    tl_plan::JobCopy jc;
-    jc.job = jobs[j];
-    jc.t_of_rhs.assign(jobs[j].t_of_rhs, jobs[j].t_of_rhs + jobs[j].n_rhs);
-    if (jobs[j].w_slices) jc.w_slices.assign(jobs[j].w_slices, jobs[j].w_slices + jobs[j].n_w_slices);
-    jc.job.t_of_rhs = jc.t_of_rhs.data();
-    jc.job.w_slices = jobs[j].w_slices ? jc.w_slices.data() : nullptr;
-    jc.V3 = vol3(jc.job.g);
-    jc.Vp = tl::padded_sites(jc.V3);
-    jc.res_index.assign(jc.job.n_rhs, -1);
-    p->max_v3 = std::max(p->max_v3, jc.V3);
-    std::map<int, std::vector<int>> by_slot;
-    for (int r = 0; r < jc.job.n_rhs; r++)
-      by_slot[slot_of(jc.job.g, jc.job.w_slices, jc.job.n_w_slices, jc.t_of_rhs[r])].push_back(r);
-    const size_t rb = align256((size_t)jc.Vp * tl::kVBytes[p->prec]);
-    for (auto& kv : by_slot) {
-      const int k = (int)kv.second.size();
-      const int ng = (k + max_width - 1) / max_width;
-      int done = 0;
-      for (int q = 0; q < ng; q++) {
-        const int nr = (k - done + (ng - q) - 1) / (ng - q);
-        tl_plan::Group gr{j, kv.first, (int)p->res.size(), nr};
-        for (int i = 0; i < nr; i++) {
-          const int r = kv.second[done + i];
-          jc.res_index[r] = (int)p->res.size();
-          p->res.push_back({j, r, kv.first, (int64_t)off});
-          off += rb;
+  try {
+    if (!c) return TL_ERR_ARG;
+    if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!jobs || n_jobs < 1) return fail(c, TL_ERR_ARG, "need at least one job");
+    if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
+    if (flags & ~(unsigned)(TL_PLAIN | TL_GRAPH | TL_AUTOTUNE)) return fail(c, TL_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & TL_PLAIN) && (flags & TL_GRAPH)) return fail(c, TL_ERR_ARG, "TL_PLAIN runs eager launches; it excludes TL_GRAPH");
+    if (n_steps < 0) return fail(c, TL_ERR_ARG, "n_steps = %d is negative", n_steps);
+    if (!std::isfinite(sigma)) return fail(c, TL_ERR_ARG, "sigma is not finite");
+    const bool one = tl::is_one(fmt_code(prec));
+    if (n_steps > 0) {
+      const double s = sigma / n_steps;
+      if (s < 0.0 || s > max_step(one))
+        return fail(c, TL_ERR_ARG, "sigma/n = %g outside [0, %s]", s, one ? "1/6" : "2/3");
+    }
+    for (int j = 0; j < n_jobs; j++) {
+      const tl_job& jb = jobs[j];
+      TL_TRY(check_geom(c, &jb.g));
+      if (!jb.W || !jb.psi) return fail(c, TL_ERR_ARG, "job %d: W and psi must be non-NULL", j);
+      if (jb.n_rhs < 1 || !jb.t_of_rhs) return fail(c, TL_ERR_ARG, "job %d: needs n_rhs >= 1 and t_of_rhs", j);
+      TL_TRY(check_wslices(c, jb.g, jb.w_slices, jb.n_w_slices));
+      for (int r = 0; r < jb.n_rhs; r++)
+        if (slot_of(jb.g, jb.w_slices, jb.n_w_slices, jb.t_of_rhs[r]) < 0)
+          return fail(c, TL_ERR_SHAPE, "job %d RHS %d: slice %d not in the two-link field", j, r, jb.t_of_rhs[r]);
+    }
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+  
+    tl_plan* p = new (std::nothrow) tl_plan();
+    if (!p) return fail(c, TL_ERR_NOMEM, "host allocation failed");
+    p->ctx = c;
+    p->prec = fmt_code(prec);
+    p->n_steps = n_steps;
+    p->sigma = sigma;
+    p->flags = flags;
+    if (n_steps > 0) step_coeffs(one, n_steps, sigma, &p->alpha, &p->beta);
+    const int max_width = (flags & TL_PLAIN) ? 1 : 4;
+  
+    // resident order: per job, per slot (in slice order), RHS in job order;
+    // groups of up to max_width RHS, balanced within a slot.
+    size_t off = 0;
+    for (int j = 0; j < n_jobs; j++) {
+      tl_plan::JobCopy jc;
+      jc.job = jobs[j];
+      jc.t_of_rhs.assign(jobs[j].t_of_rhs, jobs[j].t_of_rhs + jobs[j].n_rhs);
+      if (jobs[j].w_slices) jc.w_slices.assign(jobs[j].w_slices, jobs[j].w_slices + jobs[j].n_w_slices);
+      jc.job.t_of_rhs = jc.t_of_rhs.data();
+      jc.job.w_slices = jobs[j].w_slices ? jc.w_slices.data() : nullptr;
+      jc.V3 = vol3(jc.job.g);
+      jc.Vp = tl::padded_sites(jc.V3);
+      jc.res_index.assign(jc.job.n_rhs, -1);
+      p->max_v3 = std::max(p->max_v3, jc.V3);
+      std::map<int, std::vector<int>> by_slot;
+      for (int r = 0; r < jc.job.n_rhs; r++)
+        by_slot[slot_of(jc.job.g, jc.job.w_slices, jc.job.n_w_slices, jc.t_of_rhs[r])].push_back(r);
+      const size_t rb = align256((size_t)jc.Vp * tl::kVBytes[p->prec]);
+      for (auto& kv : by_slot) {
+        const int k = (int)kv.second.size();
+        const int ng = (k + max_width - 1) / max_width;
+        int done = 0;
+        for (int q = 0; q < ng; q++) {
+          const int nr = (k - done + (ng - q) - 1) / (ng - q);
+          tl_plan::Group gr{j, kv.first, (int)p->res.size(), nr};
+          for (int i = 0; i < nr; i++) {
+            const int r = kv.second[done + i];
+            jc.res_index[r] = (int)p->res.size();
+            p->res.push_back({j, r, kv.first, (int64_t)off});
+            off += rb;
+          }
+          done += nr;
+          p->width = std::max(p->width, nr);
+          p->groups.push_back(gr);
         }
-        done += nr;
-        p->width = std::max(p->width, nr);
-        p->groups.push_back(gr);
       }
+      p->jobs.push_back(std::move(jc));
     }
-    p->jobs.push_back(std::move(jc));
-  }
-  p->buf_bytes = std::max<size_t>(off, 256);
-
-  // device memory: two resident buffers and the tables
-  int rc = TL_OK;
-  for (int k = 0; k < 2 && rc == TL_OK; k++) {
-    void* b = nullptr;
-    rc = dev_alloc(c, &b, p->buf_bytes);
-    p->buf[k] = static_cast<char*>(b);
-  }
-  const size_t n_res = p->res.size();
-  const size_t gbytes = align256(p->groups.size() * sizeof(StepGroup));
-  const size_t obytes = align256(n_res * sizeof(int64_t));
-  const size_t rbytes = align256(n_res * sizeof(tl::RedField));
-  const size_t pbytes = align256((size_t)tl::red_partials_doubles((int)n_res, p->max_v3) * sizeof(double));
-  if (rc == TL_OK) {
-    void* t = nullptr;
-    rc = dev_alloc(c, &t, gbytes + obytes + rbytes + pbytes);
-    p->tables = static_cast<char*>(t);
-  }
-  if (rc == TL_OK) {
-    p->groups_dev = reinterpret_cast<StepGroup*>(p->tables);
-    p->packoff_dev = reinterpret_cast<int64_t*>(p->tables + gbytes);
-    p->red_dev = reinterpret_cast<tl::RedField*>(p->tables + gbytes + obytes);
-    p->partials = reinterpret_cast<double*>(p->tables + gbytes + obytes + rbytes);
-    std::vector<int64_t> po;
-    std::vector<tl::RedField> rf;
-    for (auto& jc : p->jobs) {
-      p->packoff_first.push_back((int64_t)po.size());
-      for (int r = 0; r < jc.job.n_rhs; r++) po.push_back(p->res[jc.res_index[r]].off);
+    p->buf_bytes = std::max<size_t>(off, 256);
+  
+    // device memory: two resident buffers and the tables
+    int rc = TL_OK;
+    for (int k = 0; k < 2 && rc == TL_OK; k++) {
+      void* b = nullptr;
+      rc = dev_alloc(c, &b, p->buf_bytes);
+      p->buf[k] = static_cast<char*>(b);
     }
-    for (auto& jc : p->jobs)
-      for (int r = 0; r < jc.job.n_rhs; r++) {
-        const int64_t o = p->res[jc.res_index[r]].off;
-        rf.push_back({o, o, jc.V3, jc.Vp, 0});
+    const size_t n_res = p->res.size();
+    const size_t gbytes = align256(p->groups.size() * sizeof(StepGroup));
+    const size_t obytes = align256(n_res * sizeof(int64_t));
+    const size_t rbytes = align256(n_res * sizeof(tl::RedField));
+    const size_t pbytes = align256((size_t)tl::red_partials_doubles((int)n_res, p->max_v3) * sizeof(double));
+    if (rc == TL_OK) {
+      void* t = nullptr;
+      rc = dev_alloc(c, &t, gbytes + obytes + rbytes + pbytes);
+      p->tables = static_cast<char*>(t);
+    }
+    if (rc == TL_OK) {
+      p->groups_dev = reinterpret_cast<StepGroup*>(p->tables);
+      p->packoff_dev = reinterpret_cast<int64_t*>(p->tables + gbytes);
+      p->red_dev = reinterpret_cast<tl::RedField*>(p->tables + gbytes + obytes);
+      p->partials = reinterpret_cast<double*>(p->tables + gbytes + obytes + rbytes);
+      std::vector<int64_t> po;
+      std::vector<tl::RedField> rf;
+      for (auto& jc : p->jobs) {
+        p->packoff_first.push_back((int64_t)po.size());
+        for (int r = 0; r < jc.job.n_rhs; r++) po.push_back(p->res[jc.res_index[r]].off);
       }
-    int64_t oo = 0;
-    for (auto& f : rf) {
-      f.out_off = oo;
-      oo += f.V3;
+      for (auto& jc : p->jobs)
+        for (int r = 0; r < jc.job.n_rhs; r++) {
+          const int64_t o = p->res[jc.res_index[r]].off;
+          rf.push_back({o, o, jc.V3, jc.Vp, 0});
+        }
+      int64_t oo = 0;
+      for (auto& f : rf) {
+        f.out_off = oo;
+        oo += f.V3;
+      }
+      rc = upload(c, p->packoff_dev, po.data(), po.size() * sizeof(int64_t));
+      if (rc == TL_OK) rc = upload(c, p->red_dev, rf.data(), rf.size() * sizeof(tl::RedField));
     }
-    rc = upload(c, p->packoff_dev, po.data(), po.size() * sizeof(int64_t));
-    if (rc == TL_OK) rc = upload(c, p->red_dev, rf.data(), rf.size() * sizeof(tl::RedField));
+    if (rc == TL_OK) {
+      // zero the resident buffers so tuning runs never see stale bit patterns
+      for (int k = 0; k < 2 && rc == TL_OK; k++)
+        if (hipMemsetAsync(p->buf[k], 0, p->buf_bytes, c->stream) != hipSuccess)
+          rc = fail(c, TL_ERR_HIP, "hipMemsetAsync failed");
+    }
+    if (rc == TL_OK) rc = plan_upload_groups(p, p->cfg);
+    if (rc != TL_OK) {
+      plan_free(p);
+      return rc;
+    }
+    // info
+    tl_plan_info& in = p->info;
+    in.n_groups = (int32_t)p->groups.size();
+    in.group_width = p->width;
+    in.launches_per_step = (flags & TL_PLAIN) ? in.n_groups : 1;
+    double bytes = 0.0, flops = 0.0;
+    int64_t rs = 0;
+    for (auto& gr : p->groups) {
+      const double v3 = (double)p->jobs[gr.job].V3;
+      bytes += v3 * (3.0 * tl::kWBytes[p->prec] + 2.0 * gr.nr * tl::kVBytes[p->prec]);
+      flops += v3 * (444.0 * gr.nr + (tl::is_w12(p->prec) ? 3 * 42.0 : 0.0));
+      rs += (int64_t)p->jobs[gr.job].V3 * gr.nr;
+    }
+    in.rhs_sites = rs;
+    in.bytes_per_step = bytes;
+    in.flops_per_step = flops;
+    in.resident_bytes = (int64_t)(2 * p->buf_bytes + gbytes + obytes + rbytes + pbytes);
+    *out = p;
+    return TL_OK;
+  } catch (...) {
+    return host_failure(c);
   }
-  if (rc == TL_OK) {
-    // zero the resident buffers so tuning runs never see stale bit patterns
-    for (int k = 0; k < 2 && rc == TL_OK; k++)
-      if (hipMemsetAsync(p->buf[k], 0, p->buf_bytes, c->stream) != hipSuccess)
-        rc = fail(c, TL_ERR_HIP, "hipMemsetAsync failed");
-  }
-  if (rc == TL_OK) rc = plan_upload_groups(p, p->cfg);
-  if (rc != TL_OK) {
-    plan_free(p);
-    return rc;
-  }
-  // info
-  tl_plan_info& in = p->info;
-  in.n_groups = (int32_t)p->groups.size();
-  in.group_width = p->width;
-  in.launches_per_step = (flags & TL_PLAIN) ? in.n_groups : 1;
-  double bytes = 0.0, flops = 0.0;
-  int64_t rs = 0;
-  for (auto& gr : p->groups) {
-    const double v3 = (double)p->jobs[gr.job].V3;
-    bytes += v3 * (3.0 * tl::kWBytes[p->prec] + 2.0 * gr.nr * tl::kVBytes[p->prec]);
-    flops += v3 * (444.0 * gr.nr + (tl::is_w12(p->prec) ? 3 * 42.0 : 0.0));
-    rs += (int64_t)p->jobs[gr.job].V3 * gr.nr;
-  }
-  in.rhs_sites = rs;
-  in.bytes_per_step = bytes;
-  in.flops_per_step = flops;
-  in.resident_bytes = (int64_t)(2 * p->buf_bytes + gbytes + obytes + rbytes + pbytes);
-  *out = p;
-  return TL_OK;
 }
 
 int tl_plan_load(tl_plan* p) {
-  if (!p) return TL_ERR_ARG;
-  tl_ctx* c = p->ctx;
-  DeviceGuard dg(c->device);
-  for (size_t j = 0; j < p->jobs.size(); j++) {
-    const auto& jc = p->jobs[j];
-    TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(tl::vprec(p->prec), jc.job.psi, p->buf[p->cur], p->packoff_dev + p->packoff_first[j],
-                                        jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+  try {
+    if (!p) return TL_ERR_ARG;
+    tl_ctx* c = p->ctx;
+    TL_ON_DEVICE(c);
+    for (size_t j = 0; j < p->jobs.size(); j++) {
+      const auto& jc = p->jobs[j];
+      TL_TRY(launch(c, "pack", [&] { return tl::launch_pack(tl::vprec(p->prec), jc.job.psi, p->buf[p->cur], p->packoff_dev + p->packoff_first[j],
+                                          jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+    }
+    return TL_OK;
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
   }
-  return TL_OK;
 }
 
 int tl_plan_run(tl_plan* p) {
-  if (!p) return TL_ERR_ARG;
-  tl_ctx* c = p->ctx;
-  if (p->n_steps == 0) return TL_OK;
-  DeviceGuard dg(c->device);
-  TL_TRY(plan_prepare(p));
-  if (p->flags & TL_GRAPH) {
-    TL_TRY(plan_capture(p, p->cur));
-    if (c->fault_launch) return fail(c, TL_ERR_HIP, "graph launch failed (TL_FAULT=launch)");
-    HIP_TRY(c, hipGraphLaunch(p->graph[p->cur], c->stream));
-  } else {
-    TL_TRY(plan_enqueue(p, c->stream, p->cur));
+  try {
+    if (!p) return TL_ERR_ARG;
+    tl_ctx* c = p->ctx;
+    if (p->n_steps == 0) return TL_OK;
+    TL_ON_DEVICE(c);
+    TL_TRY(plan_prepare(p));
+    if (p->flags & TL_GRAPH) {
+      TL_TRY(plan_capture(p, p->cur));
+      if (c->fault_launch) return fail(c, TL_ERR_HIP, "graph launch failed (TL_FAULT=launch)");
+      HIP_TRY(c, hipGraphLaunch(p->graph[p->cur], c->stream));
+    } else {
+      TL_TRY(plan_enqueue(p, c->stream, p->cur));
+    }
+    p->cur ^= (p->n_steps & 1);
+    return TL_OK;
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
   }
-  p->cur ^= (p->n_steps & 1);
-  return TL_OK;
 }
 
 int tl_plan_store(tl_plan* p) {
-  if (!p) return TL_ERR_ARG;
-  tl_ctx* c = p->ctx;
-  DeviceGuard dg(c->device);
-  for (size_t j = 0; j < p->jobs.size(); j++) {
-    const auto& jc = p->jobs[j];
-    TL_TRY(launch(c, "unpack", [&] { return tl::launch_unpack(tl::vprec(p->prec), p->buf[p->cur], jc.job.psi, p->packoff_dev + p->packoff_first[j],
-                                          jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+  try {
+    if (!p) return TL_ERR_ARG;
+    tl_ctx* c = p->ctx;
+    TL_ON_DEVICE(c);
+    for (size_t j = 0; j < p->jobs.size(); j++) {
+      const auto& jc = p->jobs[j];
+      TL_TRY(launch(c, "unpack", [&] { return tl::launch_unpack(tl::vprec(p->prec), p->buf[p->cur], jc.job.psi, p->packoff_dev + p->packoff_first[j],
+                                            jc.job.n_rhs, jc.V3, jc.Vp, c->stream); }));
+    }
+    return TL_OK;
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
   }
-  return TL_OK;
 }
 
 int tl_plan_reduce(tl_plan* p, int kind, const tl_plan* other, double* out) {
-  if (!p) return TL_ERR_ARG;
-  tl_ctx* c = p->ctx;
-  if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
-  if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
-  const char* b = nullptr;
-  if (kind == TL_DOT) {
-    if (!other) return fail(c, TL_ERR_ARG, "TL_DOT needs a second plan");
-    if (other->ctx != c || tl::vprec(other->prec) != tl::vprec(p->prec) || other->buf_bytes != p->buf_bytes || other->res.size() != p->res.size())
-      return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in context, precision or shape");
-    for (size_t i = 0; i < p->res.size(); i++)
-      if (other->res[i].off != p->res[i].off) return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in layout");
-    b = other->buf[other->cur];
+  try {
+    if (!p) return TL_ERR_ARG;
+    tl_ctx* c = p->ctx;
+    if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
+    if (!out) return fail(c, TL_ERR_ARG, "out is NULL");
+    const char* b = nullptr;
+    if (kind == TL_DOT) {
+      if (!other) return fail(c, TL_ERR_ARG, "TL_DOT needs a second plan");
+      if (other->ctx != c || tl::vprec(other->prec) != tl::vprec(p->prec) || other->buf_bytes != p->buf_bytes || other->res.size() != p->res.size())
+        return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in context, precision or shape");
+      for (size_t i = 0; i < p->res.size(); i++)
+        if (other->res[i].off != p->res[i].off) return fail(c, TL_ERR_ARG, "TL_DOT: plans differ in layout");
+      b = other->buf[other->cur];
+    }
+    TL_ON_DEVICE(c);
+    // a (this) is the second argument of <other, this>
+    return launch(c, "reduction", [&] { return tl::launch_reduce(kind, tl::vprec(p->prec), p->buf[p->cur], b, p->red_dev, (int)p->res.size(), p->max_v3,
+                                          p->partials, out, c->stream); });
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
   }
-  DeviceGuard dg(c->device);
-  // a (this) is the second argument of <other, this>
-  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, tl::vprec(p->prec), p->buf[p->cur], b, p->red_dev, (int)p->res.size(), p->max_v3,
-                                        p->partials, out, c->stream); });
 }
 
 int tl_plan_time(tl_plan* p, int reps, double* ms_per_step) {
-  if (!p) return TL_ERR_ARG;
-  tl_ctx* c = p->ctx;
-  if (reps < 1 || !ms_per_step) return fail(c, TL_ERR_ARG, "need reps >= 1 and an output pointer");
-  if (p->n_steps == 0) return fail(c, TL_ERR_ARG, "plan has no steps");
-  DeviceGuard dg(c->device);
-  TL_TRY(tl_plan_run(p));   // tuning and graph capture happen outside the timed region
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = TL_OK;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return fail(c, TL_ERR_HIP, "hipEventCreate failed");
+  try {
+    if (!p) return TL_ERR_ARG;
+    tl_ctx* c = p->ctx;
+    if (reps < 1 || !ms_per_step) return fail(c, TL_ERR_ARG, "need reps >= 1 and an output pointer");
+    if (p->n_steps == 0) return fail(c, TL_ERR_ARG, "plan has no steps");
+    TL_ON_DEVICE(c);
+    TL_TRY(tl_plan_run(p));   // tuning and graph capture happen outside the timed region
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TL_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(c, TL_ERR_HIP, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && rc == TL_OK; k++) rc = tl_plan_run(p);
+    (void)hipEventRecord(e1, c->stream);
+    float ms = 0.0f;
+    if (rc == TL_OK) {
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = fail(c, TL_ERR_HIP, "event timing failed");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == TL_OK) *ms_per_step = ms / ((double)reps * p->n_steps * p->info.launches_per_step);
+    return rc;
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
   }
-  (void)hipEventRecord(e0, c->stream);
-  for (int k = 0; k < reps && rc == TL_OK; k++) rc = tl_plan_run(p);
-  (void)hipEventRecord(e1, c->stream);
-  float ms = 0.0f;
-  if (rc == TL_OK) {
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-      rc = fail(c, TL_ERR_HIP, "event timing failed");
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc == TL_OK) *ms_per_step = ms / ((double)reps * p->n_steps * p->info.launches_per_step);
-  return rc;
 }
 
 int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
-  if (!p || !info) return TL_ERR_ARG;
-  *info = p->info;
-  info->n_tiles = p->n_tiles;
-  info->variant = p->cfg.variant;
-  info->block = p->cfg.block;
-  info->tz = p->cfg.tz;
-  info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
-  info->nt = p->cfg.nt;
-  info->flip = p->cfg.flip;
-  return TL_OK;
+  try {
+    if (!p || !info) return TL_ERR_ARG;
+    *info = p->info;
+    info->n_tiles = p->n_tiles;
+    info->variant = p->cfg.variant;
+    info->block = p->cfg.block;
+    info->tz = p->cfg.tz;
+    info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
+    info->nt = p->cfg.nt;
+    info->flip = p->cfg.flip;
+    return TL_OK;
+  } catch (...) {
+    return host_failure(p ? p->ctx : nullptr);
+  }
 }
 
 int tl_plan_destroy(tl_plan* p) {
-  if (!p) return TL_ERR_ARG;
-  plan_free(p);
-  return TL_OK;
+  try {
+    if (!p) return TL_ERR_ARG;
+    plan_free(p);
+    return TL_OK;
+  } catch (...) {
+    return host_failure(nullptr);
+  }
 }
 
 int tl_smear(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags) {
-  if (!c) return TL_ERR_ARG;
-  tl_plan* p = nullptr;
-  TL_TRY(tl_plan_create(c, jobs, n_jobs, n_steps, sigma, prec, flags, &p));
-  int rc = tl_plan_load(p);
-  if (rc == TL_OK) rc = tl_plan_run(p);
-  if (rc == TL_OK) rc = tl_plan_store(p);
-  plan_free(p);   // waits for the queued work before releasing the resident buffers
-  return rc;
+  try {
+    if (!c) return TL_ERR_ARG;
+    tl_plan* p = nullptr;
+    TL_TRY(tl_plan_create(c, jobs, n_jobs, n_steps, sigma, prec, flags, &p));
+    int rc = tl_plan_load(p);
+    if (rc == TL_OK) rc = tl_plan_run(p);
+    if (rc == TL_OK) rc = tl_plan_store(p);
+    plan_free(p);   // waits for the queued work before releasing the resident buffers
+    return rc;
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 int tl_reduce(tl_ctx* c, int kind, int64_t n_sites, int n_rhs, const void* psi, const void* phi, double* out) {
-  if (!c) return TL_ERR_ARG;
-  if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
-  if (n_sites < 1 || n_rhs < 1) return fail(c, TL_ERR_ARG, "need n_sites >= 1 and n_rhs >= 1");
-  if (!psi || !out || (kind == TL_DOT && !phi)) return fail(c, TL_ERR_ARG, "NULL field or output");
-  if (n_sites > (int64_t(1) << 40)) return fail(c, TL_ERR_SHAPE, "n_sites too large");
-  TL_TRY(need_device(c));
-  DeviceGuard dg(c->device);
-  std::vector<tl::RedField> rf(n_rhs);
-  for (int r = 0; r < n_rhs; r++) rf[r] = {(int64_t)r * n_sites * 3, (int64_t)r * n_sites * 3, n_sites, 0, (int64_t)r * n_sites};
-  const size_t fbytes = align256(rf.size() * sizeof(tl::RedField));
-  const size_t pbytes = (size_t)tl::red_partials_doubles(n_rhs, n_sites) * sizeof(double);
-  char* s = nullptr;
-  TL_TRY(ctx_scratch(c, fbytes + pbytes, &s));
-  TL_TRY(upload(c, s, rf.data(), rf.size() * sizeof(tl::RedField)));
-  // a = psi, b = phi: <phi, psi>
-  return launch(c, "reduction", [&] { return tl::launch_reduce(kind, -1, static_cast<const char*>(psi), static_cast<const char*>(phi),
-                                        reinterpret_cast<const tl::RedField*>(s), n_rhs, n_sites,
-                                        reinterpret_cast<double*>(s + fbytes), out, c->stream); });
+  try {
+    if (!c) return TL_ERR_ARG;
+    if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
+    if (n_sites < 1 || n_rhs < 1) return fail(c, TL_ERR_ARG, "need n_sites >= 1 and n_rhs >= 1");
+    if (!psi || !out || (kind == TL_DOT && !phi)) return fail(c, TL_ERR_ARG, "NULL field or output");
+    if (n_sites > (int64_t(1) << 40)) return fail(c, TL_ERR_SHAPE, "n_sites too large");
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+    std::vector<tl::RedField> rf(n_rhs);
+    for (int r = 0; r < n_rhs; r++) rf[r] = {(int64_t)r * n_sites * 3, (int64_t)r * n_sites * 3, n_sites, 0, (int64_t)r * n_sites};
+    const size_t fbytes = align256(rf.size() * sizeof(tl::RedField));
+    const size_t pbytes = (size_t)tl::red_partials_doubles(n_rhs, n_sites) * sizeof(double);
+    char* s = nullptr;
+    TL_TRY(ctx_scratch(c, fbytes + pbytes, &s));
+    TL_TRY(upload(c, s, rf.data(), rf.size() * sizeof(tl::RedField)));
+    // a = psi, b = phi: <phi, psi>
+    return launch(c, "reduction", [&] { return tl::launch_reduce(kind, -1, static_cast<const char*>(psi), static_cast<const char*>(phi),
+                                          reinterpret_cast<const tl::RedField*>(s), n_rhs, n_sites,
+                                          reinterpret_cast<double*>(s + fbytes), out, c->stream); });
+  } catch (...) {
+    return host_failure(c);
+  }
 }
 
 }  // extern "C"
