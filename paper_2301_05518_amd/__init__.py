@@ -77,12 +77,14 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
-def _need(t, dtype: str, numel: int, name: str, at_least: bool = False):
+def _need(t, dtype: str, numel: int, name: str, at_least: bool = False, device: int | None = None):
     """The C ABI takes raw pointers: check dtype, device, layout and size here."""
     import torch
     want = getattr(torch, dtype)
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
     if t.dtype != want:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
@@ -162,10 +164,10 @@ class Context:
         import torch
         n = int(L[3]) if slices is None else len(slices)
         nbytes = twolinks_bytes(L, prec, n)
-        _need(U, "complex128", _v3(L) * int(L[3]) * 36, "U")
+        _need(U, "complex128", _v3(L) * int(L[3]) * 36, "U", device=self.device)
         if W is None:
             W = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self._torch_device())
-        _need(W, "uint8", nbytes, "W", at_least=True)
+        _need(W, "uint8", nbytes, "W", at_least=True, device=self.device)
         arr, ns = _i32(slices)
         self._check(fn(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(U)),
                        arr, ns if slices is not None else 0, _prec(prec), ctypes.c_void_p(_ptr(W))))
@@ -174,13 +176,13 @@ class Context:
 
     def laplacian(self, L, W, prec, t, psi_in, out=None, w_slices=None):
         import torch
-        _need(psi_in, "complex128", _v3(L) * 3, "psi_in")
+        _need(psi_in, "complex128", _v3(L) * 3, "psi_in", device=self.device)
         if out is None:
             out = torch.empty_like(psi_in)
-        _need(out, "complex128", _v3(L) * 3, "out")
+        _need(out, "complex128", _v3(L) * 3, "out", device=self.device)
         nw = int(L[3]) if w_slices is None else len(w_slices)
         _check_w_format(W, prec, "W")
-        _need(W, "uint8", twolinks_bytes(L, prec, nw), "W", at_least=True)
+        _need(W, "uint8", twolinks_bytes(L, prec, nw), "W", at_least=True, device=self.device)
         arr, n = _i32(w_slices)
         self._check(self.lib.tl_laplacian(self.h, ctypes.byref(_geom(L)), ctypes.c_void_p(_ptr(W)), arr, n,
                                           _prec(prec), int(t), ctypes.c_void_p(_ptr(psi_in)),
@@ -191,10 +193,10 @@ class Context:
         arr = (_lib.Job * len(jobs))()
         keep = []
         for i, j in enumerate(jobs):
-            _need(j.psi, "complex128", len(j.t_of_rhs) * _v3(j.L) * 3, f"jobs[{i}].psi")
+            _need(j.psi, "complex128", len(j.t_of_rhs) * _v3(j.L) * 3, f"jobs[{i}].psi", device=self.device)
             nw = int(j.L[3]) if j.w_slices is None else len(j.w_slices)
             _check_w_format(j.W, prec, f"jobs[{i}].W")
-            _need(j.W, "uint8", twolinks_bytes(j.L, prec, nw), f"jobs[{i}].W", at_least=True)
+            _need(j.W, "uint8", twolinks_bytes(j.L, prec, nw), f"jobs[{i}].W", at_least=True, device=self.device)
             ts, nt = _i32(j.t_of_rhs)
             ws, nw = _i32(j.w_slices)
             keep += [ts, ws]
@@ -221,11 +223,11 @@ class Context:
         k = {"norm2": 0, "dot": 1, "site_norm": 2}[kind]
         n_rhs = psi.shape[0]
         n_sites = psi[0].numel() // 3
-        _need(psi, "complex128", n_rhs * n_sites * 3, "psi")
+        _need(psi, "complex128", n_rhs * n_sites * 3, "psi", device=self.device)
         if k == 1:
             if phi is None or phi.shape != psi.shape:
                 raise ValueError("dot needs phi of psi's shape")
-            _need(phi, "complex128", n_rhs * n_sites * 3, "phi")
+            _need(phi, "complex128", n_rhs * n_sites * 3, "phi", device=self.device)
         size = {0: n_rhs, 1: 2 * n_rhs, 2: n_rhs * n_sites}[k]
         out = torch.empty(size, dtype=torch.float64, device=psi.device)
         self._check(self.lib.tl_reduce(self.h, k, n_sites, n_rhs, ctypes.c_void_p(_ptr(psi)),

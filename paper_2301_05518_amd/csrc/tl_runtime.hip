@@ -812,6 +812,10 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
   
     tl_plan* p = new (std::nothrow) tl_plan();
     if (!p) return fail(c, TL_ERR_NOMEM, "host allocation failed");
+    struct Release {   // frees the plan on every exit but the successful one
+      tl_plan* p;
+      ~Release() { plan_free(p); }
+    } release{p};
     p->ctx = c;
     p->prec = fmt_code(prec);
     p->n_steps = n_steps;
@@ -908,10 +912,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
           rc = fail(c, TL_ERR_HIP, "hipMemsetAsync failed");
     }
     if (rc == TL_OK) rc = plan_upload_groups(p, p->cfg);
-    if (rc != TL_OK) {
-      plan_free(p);
-      return rc;
-    }
+    if (rc != TL_OK) return rc;
     // info
     tl_plan_info& in = p->info;
     in.n_groups = (int32_t)p->groups.size();
@@ -929,6 +930,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
     in.bytes_per_step = bytes;
     in.flops_per_step = flops;
     in.resident_bytes = (int64_t)(2 * p->buf_bytes + gbytes + obytes + rbytes + pbytes);
+    release.p = nullptr;
     *out = p;
     return TL_OK;
   } catch (...) {
