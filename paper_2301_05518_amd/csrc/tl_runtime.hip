@@ -404,7 +404,7 @@ int plan_autotune(tl_plan* p) {
     const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 128, 64};
     for (int block : blocks)
       for (int tz : tzs)
-        for (int grid : {0, 8 * cu})
+        for (int grid : {0, cu, 8 * cu})   // one workgroup per tile, or persistent: 1 or 8 per CU
           for (int nt : {0, 1})
             for (int flip : {0, 1}) cands.push_back({variant, block, tz, grid, nt, flip, 0});
   }
