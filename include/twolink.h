@@ -97,7 +97,11 @@ enum {
     TL_AUTOTUNE = 4u    /* time the candidate tilings once and keep the fastest (cached per context) */
 };
 
-/* reduction kinds */
+/* reduction kinds.  TL_NORM2 and TL_DOT are the spatial sums over the sites x of one
+ * time slice that make up a two-point correlation function C(t) (Sec. 1: C(t) sums the
+ * product of the operator at (t, x) and its conjugate at the source over x; contracted
+ * from smeared source and sink vectors it is such a slice sum of colour inner products);
+ * TL_SITE_NORM is the per-site magnitude of a smeared source that Fig. 1 plots. */
 enum {
     TL_NORM2 = 0,       /* per RHS: sum_x |psi(x)|^2                -> out[n_rhs] */
     TL_DOT = 1,         /* per RHS: sum_x phi(x)^dag psi(x)         -> out[2*n_rhs] (re, im) */
@@ -160,6 +164,15 @@ int tl_version(void);
  */
 int tl_create(tl_ctx **out, int device, void *stream);
 int tl_destroy(tl_ctx *ctx);
+/*
+ * Queue the context's later work on `stream` (a hipStream_t of the context's
+ * device; NULL = the null stream).  The new stream is made to wait (through an
+ * event, without blocking the host) for everything already queued on the old
+ * one, so library memory that earlier calls still use (context scratch, plan
+ * buffers) is not overwritten by later calls; the caller's own work on either
+ * stream is not otherwise ordered.  Plans created before the switch queue on the
+ * new stream from then on.  TL_ERR_HIP if the runtime refuses the event.
+ */
 int tl_set_stream(tl_ctx *ctx, void *stream);
 /* Block until the context's stream is idle; reports asynchronous device errors. */
 int tl_sync(tl_ctx *ctx);
@@ -243,7 +256,8 @@ int tl_plan_run(tl_plan *plan);
 int tl_plan_store(tl_plan *plan);
 /*
  * FP64 reduction of the resident fields (decoded from storage precision),
- * deterministic summation order.  kind: TL_NORM2, TL_DOT (needs `other`, a
+ * deterministic summation order: the slice sums of a two-point correlation
+ * function C(t) (Sec. 1) and the per-site magnitude of Fig. 1.  kind: TL_NORM2, TL_DOT (needs `other`, a
  * plan with the same jobs' shapes; <other, this> per RHS), TL_SITE_NORM.
  * out: device doubles, sized as for the kind (RHS in the order of the jobs).
  */
@@ -261,8 +275,15 @@ int tl_plan_destroy(tl_plan *plan);
 
 /*
  * FP64 reductions of natural complex128 fields psi, phi [n_rhs][n_sites][3]
- * (device).  kind as above; phi only for TL_DOT (<phi, psi> per RHS).
- * out: device doubles (n_rhs, 2*n_rhs or n_rhs*n_sites entries).
+ * (device): per RHS the slice sum of a two-point correlation function C(t)
+ * (Sec. 1; TL_NORM2, TL_DOT) or the per-site magnitude plotted in Fig. 1
+ * (TL_SITE_NORM).  kind as above; phi only for TL_DOT (<phi, psi> per RHS).
+ * The fields are flat: any set of sites (one slice, several, a sub-volume),
+ * since a sum over sites needs no geometry.
+ * out: device doubles (n_rhs, 2*n_rhs or n_rhs*n_sites entries), written.
+ * Errors: TL_ERR_ARG for an unknown kind, NULL field or output, n_sites < 1 or
+ * n_rhs < 1; TL_ERR_SHAPE for n_sites > 2^40.  Uses context scratch memory
+ * (the partial sums), grown with hipMalloc when too small.
  */
 int tl_reduce(tl_ctx *ctx, int kind, int64_t n_sites, int n_rhs, const void *psi,
               const void *phi, double *out);

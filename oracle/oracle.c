@@ -320,7 +320,8 @@ void or_smear_onelink_batch(const int L[4], const cplx *U, int n_rhs, const int 
         or_smear_onelink(L, U, t_of_rhs[r], n, sigma, psi + (long)r * 3 * V3);
 }
 
-/* sum_x |psi(x)|^2 over n_sites colour vectors, plain sequential FP64 sum. */
+/* sum_x |psi(x)|^2 over n_sites colour vectors, plain sequential FP64 sum: the slice
+ * sum over x of a two-point correlation function C(t) (Sec. 1) with sink = source. */
 double or_norm2(long n_sites, const cplx *psi)
 {
     double s = 0.0;
@@ -329,7 +330,8 @@ double or_norm2(long n_sites, const cplx *psi)
     return s;
 }
 
-/* <phi, psi> = sum_x phi(x)^dag psi(x) (conjugate-linear in phi). */
+/* <phi, psi> = sum_x phi(x)^dag psi(x) (conjugate-linear in phi): the slice sum over x
+ * of a two-point correlation function C(t) (Sec. 1) contracting two colour vectors. */
 void or_dot(long n_sites, const cplx *phi, const cplx *psi, double *re, double *im)
 {
     cplx s = 0;

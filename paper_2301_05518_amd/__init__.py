@@ -147,6 +147,12 @@ class Context:
     def sync(self):
         self._check(self.lib.tl_sync(self.h))
 
+    def set_stream(self, stream):
+        """Queue later work on a torch stream of the context's device (tl_set_stream: the new
+        stream first waits for what the context queued on the old one)."""
+        self._check(self.lib.tl_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+        self._torch_stream = stream
+
     def _torch_device(self):
         import torch
         return torch.device("cuda", self.device)

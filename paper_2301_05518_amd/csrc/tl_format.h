@@ -25,10 +25,12 @@
 //
 // F16S stores value / s as IEEE half, with s = max |real| of the site (one
 // scale per site and direction for W, per site and RHS for vectors); s = 0
-// encodes an all-zero site.  Stores round to nearest even.  FP64 values
-// headed for half or bf16 are rounded to FP32 first.  Vector quotients are
-// formed as v * RN(1/s) in FP32 (with v and s pre-multiplied by 2^64 when s is
-// subnormal); two-link quotients as v * (1/s) in FP64.
+// encodes an all-zero site.  Stores round to nearest even.  Vector quotients
+// are formed as v * RN(1/s) in FP32, rounded to FP32 and then to half (with v
+// and s pre-multiplied by 2^64 when s is subnormal); two-link quotients as
+// v * (1/s) in FP64, rounded once to half.  The 16-bit twelve-real rows are
+// rounded once from FP64 to half; FP64 values headed for bf16 are rounded to
+// FP32 first.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,8 +60,26 @@ __device__ __forceinline__ uint32_t f32_to_h(float f) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
 }
 
+// FP64 -> half in one rounding (to nearest even).
+__device__ __forceinline__ uint32_t f64_to_h(double d) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)d);
+}
+
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) { return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16); }
 __device__ __forceinline__ uint32_t pack_h(float lo, float hi) { return f32_to_h(lo) | (f32_to_h(hi) << 16); }
+// Two-link reals (FP64): half in one rounding; bf16 through FP32.
+__device__ __forceinline__ uint32_t pack_h_d(double lo, double hi) { return f64_to_h(lo) | (f64_to_h(hi) << 16); }
+__device__ __forceinline__ uint32_t pack_bf16_d(double lo, double hi) { return pack_bf16((float)lo, (float)hi); }
+
+// FP32 product rounded to FP32.  The empty asm makes the rounded product a value the
+// compiler has to materialise: a product that is then converted to half would otherwise
+// be fused with the conversion into one mixed-precision FMA (v_fma_mixlo_f16), which
+// rounds once, to half -- not the vector format's definition (FP32 quotient, then half).
+__device__ __forceinline__ float mul_f32(float a, float b) {
+  float p = a * b;
+  asm("" : "+v"(p));
+  return p;
+}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
@@ -206,7 +226,7 @@ template <> struct Fmt<F16S> {
     const double inv = s > 0.0f ? 1.0 / (double)s : 0.0;
     uint32_t w[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++) w[k] = pack_h((float)(m[2 * k] * inv), (float)(m[2 * k + 1] * inv));
+    for (int k = 0; k < 9; k++) w[k] = pack_h_d(m[2 * k] * inv, m[2 * k + 1] * inv);
     reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
     reinterpret_cast<uint4*>(b + 16 * Vp)[i] = make_uint4(w[4], w[5], w[6], w[7]);
     reinterpret_cast<uint2*>(b + 32 * Vp)[i] = make_uint2(w[8], __float_as_uint(s));
@@ -235,7 +255,7 @@ template <> struct Fmt<F16S> {
     const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
     const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
 #pragma unroll
-    for (int c = 0; c < 6; c++) f[c] = (f[c] * pre) * inv;
+    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
     put<NT>(reinterpret_cast<v4u*>(b) + i,
             v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
   }
@@ -321,7 +341,7 @@ template <> struct Fmt<F32 | W12> : Fmt<F32> {
 };
 
 // 16-bit twelve-real forms: twelve values in a 16-byte and an 8-byte plane.
-template <uint32_t (*Pack)(float, float), float (*Unpack)(uint32_t)>
+template <uint32_t (*Pack)(double, double), float (*Unpack)(uint32_t)>
 struct Fmt16W12 {
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) {
@@ -338,21 +358,21 @@ struct Fmt16W12 {
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
     uint32_t w[6];
 #pragma unroll
-    for (int k = 0; k < 6; k++) w[k] = Pack((float)m[2 * k], (float)m[2 * k + 1]);
+    for (int k = 0; k < 6; k++) w[k] = Pack(m[2 * k], m[2 * k + 1]);
     reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
     reinterpret_cast<uint2*>(b + 16 * Vp)[i] = make_uint2(w[4], w[5]);
   }
 };
 
 template <> struct Fmt<F16S | W12> : Fmt<F16S> {
-  using W = Fmt16W12<pack_h, h_to_f32>;
+  using W = Fmt16W12<pack_h_d, h_to_f32>;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) { W::load_w(b, Vp, i, m); }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) { W::store_w(b, Vp, i, m); }
 };
 
 template <> struct Fmt<BF16 | W12> : Fmt<BF16> {
-  using W = Fmt16W12<pack_bf16, bf16_to_f32>;
+  using W = Fmt16W12<pack_bf16_d, bf16_to_f32>;
   template <typename T>
   __device__ static void load_w(const char* __restrict__ b, int64_t Vp, int64_t i, T (&m)[18]) { W::load_w(b, Vp, i, m); }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) { W::store_w(b, Vp, i, m); }
@@ -499,7 +519,7 @@ template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
     const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
     const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
 #pragma unroll
-    for (int c = 0; c < 6; c++) f[c] = (f[c] * pre) * inv;
+    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
     put<NT>(reinterpret_cast<v4u*>(pl[0] + i * 16u),
             v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
   }

@@ -626,7 +626,20 @@ int tl_destroy(tl_ctx* c) {
 int tl_set_stream(tl_ctx* c, void* stream) {
   try {
     if (!c) return TL_ERR_ARG;
-    c->stream = static_cast<hipStream_t>(stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (c->device >= 0 && s != c->stream) {
+      // Context scratch and plan buffers are reused in stream order.  Work already queued on
+      // the old stream may still read them, so the new stream waits for it (an event, no host
+      // wait) before anything queued through this context runs there.
+      TL_ON_DEVICE(c);
+      hipEvent_t ev = nullptr;
+      HIP_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      hipError_t e = hipEventRecord(ev, c->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+      (void)hipEventDestroy(ev);
+      if (e != hipSuccess) return fail(c, TL_ERR_HIP, "ordering the new stream after the old: %s", hipGetErrorString(e));
+    }
+    c->stream = s;
     return TL_OK;
   } catch (...) {
     return host_failure(c);

@@ -103,3 +103,73 @@ def storage_round_vectors(psi: np.ndarray, prec: str) -> np.ndarray:
         raise ValueError(prec)
     out = out.reshape(psi.shape[:-1] + (3, 2))
     return out[..., 0] + 1j * out[..., 1]
+
+
+# ---------------------------------------------------------------- link storage model
+
+def _f32(x: np.ndarray) -> np.ndarray:
+    return np.asarray(x, np.float64).astype(np.float32)
+
+
+def _bf16_round(x: np.ndarray) -> np.ndarray:
+    """FP64 -> FP32 (nearest) -> bf16 (nearest even), back to float64."""
+    return _bf16_to_f32(f32_to_bf16_rne(_f32(x))).astype(np.float64)
+
+
+def _half_round(x: np.ndarray) -> np.ndarray:
+    """FP64 -> IEEE half (nearest even, one rounding), back to float64."""
+    return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
+
+
+def storage_round_links(m: np.ndarray, prec: str) -> np.ndarray:
+    """What storing complex128 3x3 link matrices [..][3][3] in `prec` and reading them back gives.
+
+    From the format description: FP32 and BF16 round every real to nearest (BF16 through
+    FP32); F16S divides the 18 reals of a matrix by s = max |real| (rounded to FP32), forms the
+    quotient in FP64, rounds it once to half, and decodes half * s in FP32.  The
+    twelve-real forms ("<prec>-w12") store rows 0 and 1 (16-bit ones with no scale) and the
+    reader rebuilds row 2 as conj(row0 x row1), evaluated here in FP64."""
+    base, w12 = (prec[:-4], True) if prec.endswith("-w12") else (prec, False)
+    re = np.stack([m.real, m.imag], axis=-1).reshape(m.shape[:-2] + (18,))
+    if w12:
+        rows = re[..., :12]
+        if base == "f64":
+            r = rows.copy()
+        elif base == "f32":
+            r = _f32(rows).astype(np.float64)
+        elif base == "bf16":
+            r = _bf16_round(rows)
+        elif base == "f16s":
+            r = _half_round(rows)
+        else:
+            raise ValueError(prec)
+        c = (r[..., 0::2] + 1j * r[..., 1::2]).reshape(m.shape[:-2] + (2, 3))
+        a, b = c[..., 0, :], c[..., 1, :]
+        third = np.conj(np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                                  a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                                  a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], axis=-1))
+        return np.concatenate([c, third[..., None, :]], axis=-2)
+    if base == "f64":
+        out = re
+    elif base == "f32":
+        out = _f32(re).astype(np.float64)
+    elif base == "bf16":
+        out = _bf16_round(re)
+    elif base == "f16s":
+        s = _f32(np.max(np.abs(re), axis=-1, keepdims=True))
+        inv = np.where(s > 0, 1.0 / np.where(s > 0, s.astype(np.float64), 1.0), 0.0)
+        h = (re * inv).astype(np.float16)
+        out = (h.astype(np.float32) * s).astype(np.float64)
+    else:
+        raise ValueError(prec)
+    c = out[..., 0::2] + 1j * out[..., 1::2]
+    return c.reshape(m.shape)
+
+
+def ulp(x: np.ndarray, fmt: str) -> np.ndarray:
+    """Spacing of the storage format's numbers at magnitude |x| (float64 array)."""
+    p, emin = {"f32": (23, -126), "bf16": (7, -126), "half": (10, -14)}[fmt]
+    ax = np.abs(np.asarray(x, np.float64))
+    e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    e = np.where(ax > 0, np.maximum(e, emin), emin)
+    return np.exp2(e - p)

@@ -184,6 +184,34 @@ def test_side_stream_and_second_context(ctx, orc, torch):
         c2.close()
 
 
+def test_stream_switch_orders_scratch(orc, torch):
+    """tl_set_stream between two Laplacians of different shapes: the second call reuses the
+    context scratch (its table upload and pack) while the first may still run on the old
+    stream; the switch makes the new stream wait, so both results are right."""
+    import paper_2301_05518_amd as tl
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    c = tl.Context(0, stream=s1)
+    try:
+        La, Lb = (48, 48, 40, 1), (10, 6, 8, 1)
+        Ua, Ub = haar(La, 31), haar(Lb, 32)
+        pa = synth.random_field(rng(31), (La[2], La[1], La[0], 3))
+        pb = synth.random_field(rng(32), (Lb[2], Lb[1], Lb[0], 3))
+        da, db = to_dev(pa), to_dev(pb)
+        Wa = c.build_twolinks(La, to_dev(Ua), "f64")
+        Wb = c.build_twolinks(Lb, to_dev(Ub), "f64")
+        oa, ob = torch.empty_like(da), torch.empty_like(db)
+        torch.cuda.synchronize()
+        c.laplacian(La, Wa, "f64", 0, da, out=oa)
+        c.set_stream(s2)
+        c.laplacian(Lb, Wb, "f64", 0, db, out=ob)
+        torch.cuda.synchronize()
+        assert checks.max_rel(oa.cpu().numpy(), orc.laplacian(orc.build_twolinks(Ua), 0, pa)) < 1e-14
+        assert checks.max_rel(ob.cpu().numpy(), orc.laplacian(orc.build_twolinks(Ub), 0, pb)) < 1e-14
+    finally:
+        c.close()
+
+
 VARIANT_TILES = ["0,64,1,0", "0,128,3,256", "1,64,4,0", "1,128,5,512", "2,64,4,0", "2,128,3,0",
                  "2,192,16,256", "2,64,1,8", "3,64,1,0", "3,64,2,0", "3,128,5,0", "3,256,16,0", "3,64,4,8",
                  "4,64,1,0", "4,256,3,16", "4,128,2,0", "2,64,16,0,1", "0,64,2,0,1", "4,64,2,0,1",
@@ -405,6 +433,27 @@ def test_zero_steps_is_storage_roundtrip(ctx, torch, prec):
     psi[2, 1, 1, 2] = (1e-30, 2e-31, 0.0)
     out = gpu_smear(ctx, [(L, U, [0, 1, 0], psi)], 0, 0.0, prec)[0]
     assert np.array_equal(out, packed.storage_round_vectors(psi, prec))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_storage_roundtrip_large(ctx, torch, prec):
+    """The round trip on 147k reals with per-site magnitudes over four decades.  For F16S the
+    quotient v * RN(1/s) is rounded to FP32 and then to half; rounding the exact product once,
+    to half, gives a different code in about one real in 10^4, so this size tells the two apart."""
+    L = (32, 16, 16, 1)
+    U = haar(L, 71)
+    r = rng(71)
+    psi = synth.random_field(r, (3, L[2], L[1], L[0], 3))
+    psi *= np.exp2(r.uniform(-6.0, 6.0, size=psi.shape[:-1]))[..., None]
+    out = gpu_smear(ctx, [(L, U, [0, 0, 0], psi)], 0, 0.0, prec)[0]
+    want = packed.storage_round_vectors(psi, prec)
+    if prec == "f16s":
+        re = np.stack([psi.real, psi.imag], -1).reshape(psi.shape[:-1] + (6,)).astype(np.float32)
+        mx = np.abs(re).max(-1, keepdims=True)
+        once = (re.astype(np.float64) * (np.float32(1.0) / mx).astype(np.float64)).astype(np.float16)
+        twice = (re * (np.float32(1.0) / mx)).astype(np.float16)
+        log(f"f16s: {int(np.sum(once != twice))} reals where one rounding would differ")
+    assert np.array_equal(out, want)
 
 
 # ------------------------------------------------------------------ reductions
