@@ -288,6 +288,23 @@ int tl_plan_destroy(tl_plan *plan);
 int tl_reduce(tl_ctx *ctx, int kind, int64_t n_sites, int n_rhs, const void *psi,
               const void *phi, double *out);
 
+/*
+ * tl_reduce without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Arguments, results (bit for bit) and errors as for
+ * tl_reduce, plus: TL_ERR_SHAPE, before any device work, when the first pass
+ * needs more partial sums than the fixed area holds, i.e. for TL_NORM2 and
+ * TL_DOT n_rhs * ceil(n_sites / 4096) must not exceed 65536 (TL_SITE_NORM has
+ * no limit); TL_ERR_HIP if the area's address could not be looked up when the
+ * context was created.  The partial sums live in one fixed device array of
+ * 1 MiB per device (held until the process ends), shared by every context and
+ * call on that device: calls that overlap on one device (other streams, other
+ * threads) race and give wrong results; calls queued on one stream are
+ * ordered.  No host-to-device copy, no hipMalloc, no hipFree, no memset.
+ */
+int tl_reduce_noalloc(tl_ctx *ctx, int kind, int64_t n_sites, int n_rhs, const void *psi,
+                      const void *phi, double *out);
+
 #ifdef __cplusplus
 }
 #endif

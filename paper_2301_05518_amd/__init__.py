@@ -223,8 +223,16 @@ class Context:
     def plan(self, jobs: Sequence[Job], n_steps: int, sigma: float, prec="f32", flags: int = 0) -> "Plan":
         return Plan(self, jobs, n_steps, sigma, prec, flags)
 
-    def reduce(self, kind: str, psi, phi=None):
+    def reduce(self, kind: str, psi, phi=None, out=None):
         """FP64 reductions of complex128 fields [n_rhs][...][3]: 'norm2', 'dot' (<phi, psi>), 'site_norm'."""
+        return self._reduce(self.lib.tl_reduce, kind, psi, phi, out)
+
+    def reduce_noalloc(self, kind: str, psi, phi=None, out=None):
+        """As reduce, through tl_reduce_noalloc (no library allocation; pass `out`, a float64 tensor
+        of n_rhs, 2 n_rhs or n_rhs * n_sites entries, to allocate nothing here either)."""
+        return self._reduce(self.lib.tl_reduce_noalloc, kind, psi, phi, out)
+
+    def _reduce(self, fn, kind: str, psi, phi, out):
         import torch
         k = {"norm2": 0, "dot": 1, "site_norm": 2}[kind]
         n_rhs = psi.shape[0]
@@ -235,10 +243,12 @@ class Context:
                 raise ValueError("dot needs phi of psi's shape")
             _need(phi, "complex128", n_rhs * n_sites * 3, "phi", device=self.device)
         size = {0: n_rhs, 1: 2 * n_rhs, 2: n_rhs * n_sites}[k]
-        out = torch.empty(size, dtype=torch.float64, device=psi.device)
-        self._check(self.lib.tl_reduce(self.h, k, n_sites, n_rhs, ctypes.c_void_p(_ptr(psi)),
-                                       ctypes.c_void_p(_ptr(phi) if phi is not None else None),
-                                       ctypes.c_void_p(_ptr(out))))
+        if out is None:
+            out = torch.empty(size, dtype=torch.float64, device=psi.device)
+        _need(out, "float64", size, "out", device=self.device)
+        self._check(fn(self.h, k, n_sites, n_rhs, ctypes.c_void_p(_ptr(psi)),
+                       ctypes.c_void_p(_ptr(phi) if phi is not None else None),
+                       ctypes.c_void_p(_ptr(out))))
         if k == 1:
             return torch.complex(out[0::2], out[1::2])
         if k == 2:

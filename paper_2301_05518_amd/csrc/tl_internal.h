@@ -135,6 +135,16 @@ int64_t red_partials_doubles(int n_rhs, int64_t max_v3);
 hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const RedField* fields_dev,
                          int n_rhs, int64_t max_v3, double* partials, double* out, hipStream_t stream);
 
+// No-allocation reductions (tl_reduce_noalloc): natural complex128 fields [n_rhs][n_sites][3]
+// reduced with their first-pass partial sums in a fixed per-device array of kNoallocPartials
+// doubles.  noalloc_scratch_init looks up this device's copy (the device must be current);
+// noalloc_scratch returns it, or NULL before the lookup.
+constexpr int64_t kNoallocPartials = 2 * 65536;
+hipError_t noalloc_scratch_init(int device);
+double* noalloc_scratch(int device);
+hipError_t launch_reduce_flat(int kind, const void* psi, const void* phi, int64_t n_sites, int n_rhs,
+                              double* partials, double* out, hipStream_t stream);
+
 // flag[0] = 1 if the n_bytes at a and b differ anywhere (flag must be cleared by the caller).
 hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t stream);
 

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "tl_format.h"
 #include "tl_internal.h"
 #include "tl_step.h"
@@ -147,17 +150,30 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return s;
 }
 
+// Where the fields of a reduction lie: a device table with one entry per RHS, or natural
+// fields of n sites each, one after the other (the entry is then computed, no table).
+struct TableFields {
+  const RedField* f;
+  __device__ RedField operator()(int r) const { return f[r]; }
+};
+struct FlatFields {
+  int64_t n;
+  __device__ RedField operator()(int r) const {
+    const int64_t o = (int64_t)r * n;
+    return RedField{3 * o, 3 * o, n, 0, o};
+  }
+};
+
 // partials[(r * nb + b) * 2 + {0,1}]: block b of RHS r.  Fixed site-to-block
 // and in-block orders make the result reproducible run to run.
-template <class LD>
+template <class LD, class F>
 __global__ __launch_bounds__(kRedBlock) void reduce_partial_kernel(int kind, const char* __restrict__ a,
-                                                                   const char* __restrict__ b,
-                                                                   const RedField* __restrict__ f,
+                                                                   const char* __restrict__ b, F f,
                                                                    double* __restrict__ partials) {
   __shared__ double lds[kRedBlock / 64];
   const int r = blockIdx.y;
   const int nb = gridDim.x;
-  const RedField fr = f[r];
+  const RedField fr = f(r);
   const int64_t s0 = (int64_t)blockIdx.x * kRedSitesPerBlock;
   const int64_t s1 = min(s0 + (int64_t)kRedSitesPerBlock, fr.V3);
   double re = 0.0, im = 0.0;
@@ -204,11 +220,11 @@ __global__ void reduce_finish_kernel(int kind, const double* __restrict__ partia
   }
 }
 
-template <class LD>
-__global__ __launch_bounds__(kRedBlock) void site_norm_kernel(const char* __restrict__ a, const RedField* __restrict__ f,
+template <class LD, class F>
+__global__ __launch_bounds__(kRedBlock) void site_norm_kernel(const char* __restrict__ a, F f,
                                                               double* __restrict__ out) {
   const int r = blockIdx.y;
-  const RedField fr = f[r];
+  const RedField fr = f(r);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= fr.V3) return;
   double v[6];
@@ -321,8 +337,11 @@ int64_t red_partials_doubles(int n_rhs, int64_t max_v3) {
   return 2 * nb * std::max(n_rhs, 1);
 }
 
-hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const RedField* f, int n_rhs,
-                         int64_t max_v3, double* partials, double* out, hipStream_t s) {
+namespace {
+
+template <class F>
+hipError_t reduce_with(int kind, int prec, const char* a, const char* b, F f, int n_rhs, int64_t max_v3,
+                       double* partials, double* out, hipStream_t s) {
   if (n_rhs <= 0 || max_v3 <= 0) return hipSuccess;
   if (kind == 2) {
     const dim3 grid((unsigned)((max_v3 + kRedBlock - 1) / kRedBlock), (unsigned)n_rhs);
@@ -350,6 +369,48 @@ hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const
   if (e != hipSuccess) return e;
   reduce_finish_kernel<<<(n_rhs + 63) / 64, 64, 0, s>>>(kind, partials, nb, n_rhs, out);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_reduce(int kind, int prec, const char* a, const char* b, const RedField* f, int n_rhs,
+                         int64_t max_v3, double* partials, double* out, hipStream_t s) {
+  return reduce_with(kind, prec, a, b, TableFields{f}, n_rhs, max_v3, partials, out, s);
+}
+
+// ------------------------------------------------------------------ no-allocation reductions
+
+// Partial sums of tl_reduce_noalloc: a fixed device array, one copy per device, held until
+// the process ends.  Host code never passes the array's name to a kernel (that is a host-side
+// stand-in, not a device address): it uses the address hipGetSymbolAddress gives on each
+// device, looked up once per device when a context is created there.
+static __device__ __align__(256) double scratch[kNoallocPartials];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, double*> g_noalloc_ptr;   // device -> address of its copy of `scratch`
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr.count(device)) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_noalloc_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(device);
+  return it == g_noalloc_ptr.end() ? nullptr : it->second;
+}
+
+hipError_t launch_reduce_flat(int kind, const void* psi, const void* phi, int64_t n_sites, int n_rhs,
+                              double* partials, double* out, hipStream_t s) {
+  return reduce_with(kind, -1, static_cast<const char*>(psi), static_cast<const char*>(phi), FlatFields{n_sites},
+                     n_rhs, n_sites, partials, out, s);
 }
 
 hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t s) {

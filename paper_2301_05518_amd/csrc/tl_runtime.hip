@@ -37,6 +37,8 @@ struct tl_ctx {
   bool big_lds = false;       // dynamic-LDS limit raised for the LDS-staged step kernels
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  double* noalloc = nullptr;  // this device's fixed partial-sum area of tl_reduce_noalloc
+  std::string noalloc_err;    // why it is missing (lookup failed at tl_create)
   std::map<std::string, StepConfig> tune;  // tuned step configurations by workload key
 };
 
@@ -594,6 +596,15 @@ int tl_create(tl_ctx** out, int device, void* stream) {
       }
       c->big_lds = tl::init_kernel_attributes() == hipSuccess;
       (void)hipGetLastError();
+      // the fixed device area of tl_reduce_noalloc: its address on this device, looked up
+      // once per device; a failure here only disables that entry point
+      const hipError_t ne = tl::noalloc_scratch_init(device);
+      c->noalloc = tl::noalloc_scratch(device);
+      if (ne != hipSuccess || !c->noalloc) {
+        c->noalloc = nullptr;
+        c->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(ne);
+        (void)hipGetLastError();
+      }
     }
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
@@ -1101,13 +1112,45 @@ int tl_smear(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigm
   }
 }
 
+namespace {
+
+int check_reduce_args(tl_ctx* c, int kind, int64_t n_sites, int n_rhs, const void* psi, const void* phi,
+                      const double* out) {
+  if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
+  if (n_sites < 1 || n_rhs < 1) return fail(c, TL_ERR_ARG, "need n_sites >= 1 and n_rhs >= 1");
+  if (!psi || !out || (kind == TL_DOT && !phi)) return fail(c, TL_ERR_ARG, "NULL field or output");
+  if (n_sites > (int64_t(1) << 40)) return fail(c, TL_ERR_SHAPE, "n_sites too large");
+  return TL_OK;
+}
+
+}  // namespace
+
+int tl_reduce_noalloc(tl_ctx* c, int kind, int64_t n_sites, int n_rhs, const void* psi, const void* phi,
+                      double* out) {
+  try {
+    if (!c) return TL_ERR_ARG;
+    TL_TRY(check_reduce_args(c, kind, n_sites, n_rhs, psi, phi, out));
+    if (kind != TL_SITE_NORM) {
+      const int64_t need = tl::red_partials_doubles(n_rhs, n_sites);
+      if (need > tl::kNoallocPartials)
+        return fail(c, TL_ERR_SHAPE,
+                    "tl_reduce_noalloc: %lld partial sums needed, the fixed area holds %lld "
+                    "(n_rhs * ceil(n_sites / 4096) must not exceed %lld)",
+                    (long long)need, (long long)tl::kNoallocPartials, (long long)(tl::kNoallocPartials / 2));
+    }
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+    if (!c->noalloc) return fail(c, TL_ERR_HIP, "no fixed reduction area on device %d (%s)", c->device, c->noalloc_err.c_str());
+    return launch(c, "reduction", [&] { return tl::launch_reduce_flat(kind, psi, phi, n_sites, n_rhs, c->noalloc, out, c->stream); });
+  } catch (...) {
+    return host_failure(c);
+  }
+}
+
 int tl_reduce(tl_ctx* c, int kind, int64_t n_sites, int n_rhs, const void* psi, const void* phi, double* out) {
   try {
     if (!c) return TL_ERR_ARG;
-    if (kind < TL_NORM2 || kind > TL_SITE_NORM) return fail(c, TL_ERR_ARG, "unknown reduction kind %d", kind);
-    if (n_sites < 1 || n_rhs < 1) return fail(c, TL_ERR_ARG, "need n_sites >= 1 and n_rhs >= 1");
-    if (!psi || !out || (kind == TL_DOT && !phi)) return fail(c, TL_ERR_ARG, "NULL field or output");
-    if (n_sites > (int64_t(1) << 40)) return fail(c, TL_ERR_SHAPE, "n_sites too large");
+    TL_TRY(check_reduce_args(c, kind, n_sites, n_rhs, psi, phi, out));
     TL_TRY(need_device(c));
     TL_ON_DEVICE(c);
     std::vector<tl::RedField> rf(n_rhs);

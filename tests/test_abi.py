@@ -205,6 +205,20 @@ def test_reduce_validation(lib, hctx):
     assert lib.tl_reduce(hctx, 0, 10, 1, FAKE, None, out) == -4
 
 
+def test_reduce_noalloc_validation(lib, hctx):
+    out = ctypes.c_void_p(0x30000)
+    f = lib.tl_reduce_noalloc
+    assert f(hctx, 3, 10, 1, FAKE, None, out) == -1
+    assert f(hctx, 1, 10, 1, FAKE, None, out) == -1      # dot needs phi
+    assert f(hctx, 0, 10, 0, FAKE, None, out) == -1
+    # the fixed partial-sum area holds 65536 (re, im) pairs: n_rhs * ceil(n_sites / 4096)
+    assert f(hctx, 0, 4096 * 64, 1024, FAKE, None, out) == -4      # exactly full: valid, host-only
+    assert f(hctx, 0, 4096 * 64 + 1, 1024, FAKE, None, out) == -2
+    assert b"fixed area" in lib.tl_last_error(hctx)
+    assert f(hctx, 1, 4096 * 65, 1024, FAKE, FAKE, out) == -2
+    assert f(hctx, 2, 4096 * 65, 1024, FAKE, None, out) == -4      # site norms need no partial sums
+
+
 def test_null_context(lib):
     g = geom(4, 4, 4, 4)
     assert lib.tl_build_twolinks(None, ctypes.byref(g), FAKE, None, 0, 1, FAKE) == -1
