@@ -27,6 +27,8 @@ import sys
 import time
 from concurrent.futures import ThreadPoolExecutor
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,6 +59,12 @@ def parse():
     ap.add_argument("--tile", default=None, help="fixed step tiling 'variant,block,tz,grid' (no tuning)")
     ap.add_argument("--prec", choices=("f64", "f32", "f16s", "bf16"), default=None,
                     help="storage precision instead of the workload's first one (e.g. f16s for workload 2)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (their rates, roofline fractions and oracle errors)")
+    ap.add_argument("--build-only", action="store_true",
+                    help="time only the two-link build of every slice of the workload's first lattice "
+                         "(profiling runs of the build kernel)")
+    ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script into "
                          "profiles/traffic.json and exit")
@@ -210,8 +218,195 @@ def cpu_baseline(lat, wl, U_dev, n_rhs_sample, onelink=False, gpu_out=None):
     return cpu, acc
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample_child():
+    """Child process (no GPU): the oracle on one RHS of the benchmark workload, whatever threads
+    OMP_NUM_THREADS gives it; prints one JSON line."""
+    from oracle import core
+    from paper_2301_05518_amd import synth
+    wl = synth.workload(3)
+    lat = wl.lattices[0]
+    t = lat.t_of_rhs[0]
+    orc = core.get()
+    u = synth.gauge_slice(lat.L, lat.links, lat.link_seed, t)[None]
+    t0 = time.perf_counter()
+    W = orc.build_twolinks(u)
+    orc.smear(W, 0, wl.n_steps, wl.sigma, lat.source(0))
+    dt = time.perf_counter() - t0
+    print(json.dumps({"value": lat.V3 * wl.n_steps / dt, "seconds": dt,
+                      "sample": f"RHS 0 (one 64^3 slice) x {wl.n_steps} steps incl. its two-link build, FP64"}))
+
+
+def oracle_single_thread():
+    """The oracle's single-thread rate, timed in a child process with OMP_NUM_THREADS=1."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample"], env=env,
+                         capture_output=True, text=True, timeout=300)
+    if res.returncode != 0:
+        log(f"[bench] single-thread oracle sample failed: {res.stderr[-500:]}")
+        return None
+    rec = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": rec["value"], "unit": "RHS-site-updates/s", "cores": 1, "sample": rec["sample"],
+            "seconds": round(rec["seconds"], 2)}
+
+
+STEP_KINDS = 2    # the step kernels' load and store kinds: cached loads, nontemporal stores
+
+
+def stream_ceiling(ctx, torch, dev, nbytes):
+    """Streaming probe of the library (tl_stream_time): four input planes, one output plane, the
+    step's read/write mix, over nbytes in all; every load/store kind and three grid sizes."""
+    nbytes = max(nbytes // (5 * 256) * 5 * 256, 5 * 256)
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    kinds_name = {0: "cached loads, cached stores", 1: "nontemporal loads, cached stores",
+                  2: "cached loads, nontemporal stores", 3: "nontemporal loads, nontemporal stores"}
+    rows = []
+    for kinds in range(4):
+        for per_cu in (4, 16, 64):
+            ms = ctx.stream_time(buf, n_in=4, kinds=kinds, grid=per_cu * n_cu, reps=5)
+            rows.append({"kinds": kinds_name[kinds], "grid": per_cu * n_cu,
+                         "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1), "step_kinds": kinds == STEP_KINDS})
+    del buf
+    torch.cuda.empty_cache()
+    best = max(rows, key=lambda r: r["GBs"])
+    same = max((r for r in rows if r["step_kinds"]), key=lambda r: r["GBs"])
+    return {"ceiling_GBs": best["GBs"], "ceiling_kinds": best["kinds"], "step_kinds_GBs": same["GBs"],
+            "bytes": nbytes, "mix": "4 reads : 1 write", "configs": rows}
+
+
+def compact_lattice(lat):
+    """The lattice cut down to the slices its RHS live on: links of those slices only (drawn as in
+    the full field), the RHS's slices renumbered.  A step on a slice never reads another slice,
+    so the smearing work and its result are those of the full lattice."""
+    from paper_2301_05518_amd import synth
+    slices = sorted(set(lat.t_of_rhs))
+    U = np.stack([synth.gauge_slice(lat.L, lat.links, lat.link_seed, t) for t in slices])
+    L = tuple(lat.L[:3]) + (len(slices),)
+    return L, U, [slices.index(t) for t in lat.t_of_rhs]
+
+
+def measure_workload(ctx, torch, tl, dev, index, prec, plain=False, passes=5):
+    """Step and pass rates, roofline fraction and oracle error of one of the other workloads."""
+    from oracle import checks, core
+    from paper_2301_05518_amd import synth
+    wl = synth.workload(index)
+    orc = core.get()
+    lats = [compact_lattice(lat) for lat in wl.lattices]
+    srcs = [lat.sources_array() for lat in wl.lattices]
+    jobs = []
+    for (L, U, ts), src in zip(lats, srcs):
+        Ud = torch.from_numpy(U).to(dev)
+        jobs.append((L, Ud, ts, torch.from_numpy(src).to(dev)))
+    tjobs = [tl.Job(L, ctx.build_twolinks(L, Ud, prec), ts, psi) for L, Ud, ts, psi in jobs]
+    plan = ctx.plan(tjobs, wl.n_steps, wl.sigma, prec, tl.TL_GRAPH | tl.TL_AUTOTUNE)
+    # one pass from the sources, checked against the oracle on every RHS
+    plan.load()
+    plan.run()
+    plan.store()
+    torch.cuda.synchronize()
+    mr = l2 = 0.0
+    for (L, U, ts), j, src in zip(lats, tjobs, srcs):
+        out = j.psi.cpu().numpy()
+        Wo = orc.build_twolinks(U)
+        for r, t in enumerate(ts):
+            ref = orc.smear(Wo, t, wl.n_steps, wl.sigma, src[r])
+            mr = max(mr, checks.max_rel(out[r], ref))
+            l2 = max(l2, checks.l2_rel(out[r], ref))
+
+    def one_pass():
+        for (L, Ud, ts, _), j in zip(jobs, tjobs):
+            ctx.build_twolinks(L, Ud, prec, W=j.W)
+        plan.load()
+        plan.run()
+        plan.reduce("norm2")
+        plan.store()
+
+    one_pass()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(passes):
+        one_pass()
+    e1.record()
+    e1.synchronize()
+    pass_ms = e0.elapsed_time(e1) / passes
+    step_ms = plan.time(reps=5)
+    info = plan.info()
+    gbs = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
+    rec = {"workload": wl.name, "storage": prec, "rhs": sum(len(ts) for _, _, ts in lats),
+           "step_us": round(step_ms * 1e3, 2), "pass_ms": round(pass_ms, 4),
+           "value": wl.rhs_site_updates / (pass_ms * 1e-3),
+           "smear_only_rate": info["rhs_sites"] / (step_ms * 1e-3),
+           "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "working_set_MB": round(info["bytes_per_step"] / 1e6, 1),
+           "max_rel": mr, "l2_rel": l2,
+           "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip")}}
+    plan.close()
+    if plain:
+        pj = [tl.Job(L, ctx.build_twolinks(L, Ud, "f64"), ts, psi) for L, Ud, ts, psi in jobs]
+        p64 = ctx.plan(pj, wl.n_steps, wl.sigma, "f64", tl.TL_PLAIN | tl.TL_AUTOTUNE)
+        p64.load()
+        launch_ms = p64.time(reps=1)
+        pinfo = p64.info()
+        plain_ms = launch_ms * pinfo["launches_per_step"] * wl.n_steps
+        rec["plain_fp64_smear_ms"] = round(plain_ms, 4)
+        rec["speedup_over_plain_fp64"] = round(plain_ms / (step_ms * wl.n_steps), 3)
+        p64.close()
+    del jobs, tjobs
+    torch.cuda.empty_cache()
+    log(f"[bench]   {wl.name} {prec}: step {rec['step_us']} us ({rec['frac']:.3f} of HBM, "
+        f"{rec['working_set_MB']} MB/step), pass {rec['pass_ms']} ms, max-rel {mr:.2e}")
+    return rec
+
+
+def build_only(args):
+    """Two-link build of every slice of the workload's first lattice, timed with HIP events (the
+    command that profiles the build kernel alone), plus the calibration copy for the counters."""
+    import torch
+    import paper_2301_05518_amd as tl
+    from paper_2301_05518_amd import synth
+    dev = torch.device("cuda", 0)
+    wl = synth.workload(args.workload)
+    lat = wl.lattices[0]
+    prec = (args.prec or wl.precisions[0]) + ("-w12" if args.w12 else "")
+    log(f"[bench] build only: {lat.L}, {prec}")
+    U = links_on_device(torch, lat, dev, min(16, os.cpu_count() or 1))
+    ctx = tl.Context(0)
+    W = ctx.build_twolinks(lat.L, U, prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ctx.build_twolinks(lat.L, U, prec, W=W)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = lat.V3 * lat.L[3] * 3 * 144 + tl.twolinks_bytes(lat.L, prec, lat.L[3])
+    ca = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    torch.empty_like(ca).copy_(ca)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel": "build_twolinks", "lattice": list(lat.L), "storage": prec, "ms": round(ms, 4),
+                      "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                      "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.oracle_sample:
+        oracle_sample_child()
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, workload_key(args), args.tile)
         return
@@ -222,6 +417,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU: the path shards by time slice with no "
                                    "exchange, but multi-GPU runs are not implemented; use --gpus 1"}))
         sys.exit(2)
+    if args.build_only:
+        build_only(args)
+        return
 
     import torch
     import paper_2301_05518_amd as tl
@@ -248,6 +446,7 @@ def main():
         slices = sorted(set(lat.t_of_rhs))
         jobs_in.append((lat, U, psi, slices))
     torch.cuda.synchronize()
+    U_first = jobs_in[0][1]
     log(f"[bench] inputs resident in HBM ({time.perf_counter() - t_in:.1f} s)")
 
     ctx = tl.Context(0)
@@ -314,6 +513,11 @@ def main():
     copy_gbs = 2 * COPY_BYTES * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del ca, cb
     torch.cuda.empty_cache()
+    # achievable rate of the step's read/write mix: the library's streaming probe over as many
+    # bytes as one step moves
+    ceiling = stream_ceiling(ctx, torch, dev, int(plan.info()["bytes_per_step"]))
+    log(f"[bench] streaming probe: best {ceiling['ceiling_GBs']} GB/s ({ceiling['ceiling_kinds']}), "
+        f"{ceiling['step_kinds_GBs']} GB/s with the step's load and store kinds")
 
     # dominant kernel: the smearing step.  Its average launch duration comes from the HIP events
     # around the smearing launches inside the timed passes above (the n launches of a pass
@@ -333,7 +537,9 @@ def main():
                            "step_zpipe"][info["variant"]],
                 "algorithmic_bytes_per_launch": info["bytes_per_step"],
                 "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
-                "copy_GBs": round(copy_gbs, 1)}
+                "copy_GBs": round(copy_gbs, 1), "ceiling_GBs": ceiling["ceiling_GBs"],
+                "frac_of_ceiling": round(achieved / ceiling["ceiling_GBs"], 4),
+                "ceiling": {k: ceiling[k] for k in ("ceiling_kinds", "step_kinds_GBs", "bytes", "mix", "configs")}}
     log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
 
     # the pieces of a pass, timed alone on the same stream
@@ -411,10 +617,26 @@ def main():
         torch.cuda.empty_cache()
         log(f"[bench] twelve-real two-links: step {w_ms * 1e3:.1f} us")
 
+    # the other workloads: each on the slices its RHS live on, in its own tuned graph plan
+    extra = None
+    if not args.no_extra and args.workload == 3 and not args.onelink and not args.w12 and not args.prec:
+        log("[bench] other workloads")
+        del jobs_in, jobs
+        plan.close()
+        torch.cuda.empty_cache()
+        extra = {}
+        for key, index, pr, pl in (("8^3x8_f64", 0, "f64", False), ("32^3x64_f64", 1, "f64", True),
+                                   ("48^3x96_f32", 2, "f32", True), ("48^3x96_f16s", 2, "f16s", True),
+                                   ("uneven_bf16", 4, "bf16", True)):
+            extra[key] = measure_workload(ctx, torch, tl, dev, index, pr, plain=pl)
+
     cpu = accuracy = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
-        cpu, accuracy = cpu_baseline(wl.lattices[0], wl, jobs_in[0][1], n_sample, args.onelink, first_out)
+        cpu, accuracy = cpu_baseline(wl.lattices[0], wl, U_first, n_sample, args.onelink, first_out)
+        cpu["cpu_model"] = cpu_model()
+        if not args.onelink:
+            cpu["single_thread"] = oracle_single_thread()
         log(f"[bench] oracle {cpu['value']:.3e} /s on {cpu['cores']} threads; "
             f"max-rel {accuracy['max_rel']:.2e} against it")
 
@@ -456,10 +678,12 @@ def main():
         "smear_only_rate": smear_rate,
         "plain_fp64": plain,
         "twelve_real": w12,
+        "workloads": extra,
         "finite": finite,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
+    if extra is None:
+        plan.close()
     ctx.close()
 
 

@@ -269,6 +269,22 @@ int tl_plan_reduce(tl_plan *plan, int kind, const tl_plan *other, double *out);
  * results again. */
 int tl_plan_time(tl_plan *plan, int reps, double *ms_per_step);
 int tl_plan_get_info(const tl_plan *plan, tl_plan_info *info);
+
+/*
+ * Streaming bandwidth probe (a measurement utility beside the method): the HBM
+ * rate a plain stream reaches with the read/write mix of a smearing step, as a
+ * ceiling to set the step kernel's rate against (memory bandwidth bounds the
+ * smearing iterations, Sec. 5).  buf (device, `bytes` long, 256-byte aligned)
+ * is cut into n_in + 1 equal planes of 16-byte words; one launch writes the last
+ * plane as the FP32 sum of the first n_in (n_in bytes read per byte written).
+ * kinds: bit 0 nontemporal loads, bit 1 nontemporal stores (the step kernels
+ * load cached and store nontemporally); grid: workgroups of 256 threads (0 =
+ * 16 per compute unit).  Runs reps + 1 launches, the first untimed, and writes
+ * the average duration of one launch in ms to *ms (HIP events on the context's
+ * stream; blocks the host).  buf's contents are overwritten.
+ */
+int tl_stream_time(tl_ctx *ctx, void *buf, int64_t bytes, int n_in, int kinds, int grid, int reps,
+                   double *ms);
 int tl_plan_destroy(tl_plan *plan);
 
 /* -------------------------------------------------------- reductions */

@@ -220,6 +220,14 @@ class Context:
         self._check(self.lib.tl_smear(self.h, arr, len(jobs), int(n_steps), float(sigma), _prec(prec),
                                       int(flags)))
 
+    def stream_time(self, buf, n_in: int = 4, kinds: int = 2, grid: int = 0, reps: int = 5) -> float:
+        """ms per launch of the streaming probe over a uint8 device buffer (tl_stream_time)."""
+        _need(buf, "uint8", 1, "buf", at_least=True, device=self.device)
+        ms = ctypes.c_double()
+        self._check(self.lib.tl_stream_time(self.h, ctypes.c_void_p(_ptr(buf)), buf.numel(), int(n_in), int(kinds),
+                                            int(grid), int(reps), ctypes.byref(ms)))
+        return ms.value
+
     def plan(self, jobs: Sequence[Job], n_steps: int, sigma: float, prec="f32", flags: int = 0) -> "Plan":
         return Plan(self, jobs, n_steps, sigma, prec, flags)
 

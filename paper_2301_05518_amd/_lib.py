@@ -25,7 +25,7 @@ EXPORTS = [
     "tl_version", "tl_create", "tl_destroy", "tl_set_stream", "tl_sync", "tl_last_error",
     "tl_check_geom", "tl_twolinks_bytes", "tl_build_twolinks", "tl_pack_links", "tl_laplacian", "tl_smear",
     "tl_plan_create", "tl_plan_load", "tl_plan_run", "tl_plan_store", "tl_plan_reduce",
-    "tl_plan_time", "tl_plan_get_info", "tl_plan_destroy", "tl_reduce", "tl_reduce_noalloc",
+    "tl_plan_time", "tl_plan_get_info", "tl_plan_destroy", "tl_reduce", "tl_reduce_noalloc", "tl_stream_time",
 ]
 
 
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
         "tl_plan_destroy": (i32, [vp]),
         "tl_reduce": (i32, [vp, i32, i64, i32, vp, vp, vp]),
         "tl_reduce_noalloc": (i32, [vp, i32, i64, i32, vp, vp, vp]),
+        "tl_stream_time": (i32, [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

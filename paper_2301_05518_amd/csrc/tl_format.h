@@ -144,9 +144,9 @@ template <> struct Fmt<F64> {
     }
   }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
-    double2* p = reinterpret_cast<double2*>(b);
+    v2d* p = reinterpret_cast<v2d*>(b);
 #pragma unroll
-    for (int k = 0; k < 9; k++) p[k * Vp + i] = make_double2(m[2 * k], m[2 * k + 1]);
+    for (int k = 0; k < 9; k++) put<false>(p + k * Vp + i, v2d{m[2 * k], m[2 * k + 1]});
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
@@ -183,11 +183,11 @@ template <> struct Fmt<F32> {
     m[17] = v.y;
   }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
-    float4* p = reinterpret_cast<float4*>(b);
+    v4f* p = reinterpret_cast<v4f*>(b);
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      p[k * Vp + i] = make_float4((float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]);
-    reinterpret_cast<float2*>(b + 64 * Vp)[i] = make_float2((float)m[16], (float)m[17]);
+      put<false>(p + k * Vp + i, v4f{(float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]});
+    put<false>(reinterpret_cast<v2f*>(b + 64 * Vp) + i, v2f{(float)m[16], (float)m[17]});
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
@@ -227,9 +227,9 @@ template <> struct Fmt<F16S> {
     uint32_t w[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) w[k] = pack_h_d(m[2 * k] * inv, m[2 * k + 1] * inv);
-    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
-    reinterpret_cast<uint4*>(b + 16 * Vp)[i] = make_uint4(w[4], w[5], w[6], w[7]);
-    reinterpret_cast<uint2*>(b + 32 * Vp)[i] = make_uint2(w[8], __float_as_uint(s));
+    put<false>(reinterpret_cast<v4u*>(b) + i, v4u{w[0], w[1], w[2], w[3]});
+    put<false>(reinterpret_cast<v4u*>(b + 16 * Vp) + i, v4u{w[4], w[5], w[6], w[7]});
+    put<false>(reinterpret_cast<v2u*>(b + 32 * Vp) + i, v2u{w[8], __float_as_uint(s)});
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
@@ -280,9 +280,9 @@ template <> struct Fmt<BF16> {
     uint32_t w[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) w[k] = pack_bf16((float)m[2 * k], (float)m[2 * k + 1]);
-    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
-    reinterpret_cast<uint4*>(b + 16 * Vp)[i] = make_uint4(w[4], w[5], w[6], w[7]);
-    reinterpret_cast<uint32_t*>(b + 32 * Vp)[i] = w[8];
+    put<false>(reinterpret_cast<v4u*>(b) + i, v4u{w[0], w[1], w[2], w[3]});
+    put<false>(reinterpret_cast<v4u*>(b + 16 * Vp) + i, v4u{w[4], w[5], w[6], w[7]});
+    put<false>(reinterpret_cast<uint32_t*>(b + 32 * Vp) + i, w[8]);
   }
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
@@ -313,9 +313,9 @@ template <> struct Fmt<F64 | W12> : Fmt<F64> {
     su3_row3(m);
   }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
-    double2* p = reinterpret_cast<double2*>(b);
+    v2d* p = reinterpret_cast<v2d*>(b);
 #pragma unroll
-    for (int k = 0; k < 6; k++) p[k * Vp + i] = make_double2(m[2 * k], m[2 * k + 1]);
+    for (int k = 0; k < 6; k++) put<false>(p + k * Vp + i, v2d{m[2 * k], m[2 * k + 1]});
   }
 };
 
@@ -333,10 +333,10 @@ template <> struct Fmt<F32 | W12> : Fmt<F32> {
     su3_row3(m);
   }
   __device__ static void store_w(char* __restrict__ b, int64_t Vp, int64_t i, const double (&m)[18]) {
-    float4* p = reinterpret_cast<float4*>(b);
+    v4f* p = reinterpret_cast<v4f*>(b);
 #pragma unroll
     for (int k = 0; k < 3; k++)
-      p[k * Vp + i] = make_float4((float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]);
+      put<false>(p + k * Vp + i, v4f{(float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]});
   }
 };
 
@@ -359,8 +359,8 @@ struct Fmt16W12 {
     uint32_t w[6];
 #pragma unroll
     for (int k = 0; k < 6; k++) w[k] = Pack(m[2 * k], m[2 * k + 1]);
-    reinterpret_cast<uint4*>(b)[i] = make_uint4(w[0], w[1], w[2], w[3]);
-    reinterpret_cast<uint2*>(b + 16 * Vp)[i] = make_uint2(w[4], w[5]);
+    put<false>(reinterpret_cast<v4u*>(b) + i, v4u{w[0], w[1], w[2], w[3]});
+    put<false>(reinterpret_cast<v2u*>(b + 16 * Vp) + i, v2u{w[4], w[5]});
   }
 };
 

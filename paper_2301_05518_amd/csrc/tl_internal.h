@@ -145,6 +145,10 @@ double* noalloc_scratch(int device);
 hipError_t launch_reduce_flat(int kind, const void* psi, const void* phi, int64_t n_sites, int n_rhs,
                               double* partials, double* out, hipStream_t stream);
 
+// Streaming probe over buf cut into n_in + 1 planes of n_words 16-byte words: plane n_in =
+// sum of planes 0 .. n_in - 1.  kinds bit 0: nontemporal loads, bit 1: nontemporal stores.
+hipError_t launch_stream(void* buf, int64_t n_words, int n_in, int kinds, int grid, hipStream_t stream);
+
 // flag[0] = 1 if the n_bytes at a and b differ anywhere (flag must be cleared by the caller).
 hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t stream);
 

@@ -16,66 +16,113 @@ namespace {
 
 // ------------------------------------------------------------------ build
 
-// W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in format P; with one != 0 the links
-// U_mu(x) themselves (a one-link field).  One thread per (site, mu), mu fastest: the
-// threads of a wave read consecutive 144-byte link matrices of about 21 sites (the t links
-// between them are skipped), so a matrix's nine loads stay within lines the wave has
-// already brought into L1.
-template <int P>
-__global__ __launch_bounds__(256) void build_twolinks_kernel(const double2* __restrict__ U, int Lx, int Ly, int Lz,
-                                                              int t_first, int slot_first,
-                                                              char* __restrict__ W, int64_t Vp, int one) {
-  const int slot = slot_first + (int)blockIdx.y;
-  const int t = t_first + (int)blockIdx.y;
-  const int64_t V3 = (int64_t)Lx * Ly * Lz;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= 3 * V3) return;
-  const int64_t i = k / 3;
-  const int mu = (int)(k - 3 * i);
-  const int x = (int)(i % Lx);
-  const int y = (int)((i / Lx) % Ly);
-  const int z = (int)(i / ((int64_t)Lx * Ly));
-  const int64_t nb = mu == 0 ? ((int64_t)z * Ly + y) * Lx + wrap_step(x, 1, Lx)
-                   : mu == 1 ? ((int64_t)z * Ly + wrap_step(y, 1, Ly)) * Lx + x
-                             : ((int64_t)wrap_step(z, 1, Lz) * Ly + y) * Lx + x;
-  const int64_t base = (int64_t)t * V3;
-  constexpr int WB = kWBytes[P];
-  char* const Wm = W + ((int64_t)slot * 3 + mu) * Vp * WB;
-  const double2* A = U + ((base + i) * 4 + mu) * 9;
-  double2 a[9];
+constexpr int kBuildSites = 21;                    // sites per chunk: 63 (site, mu) pairs, one per lane
+constexpr int kBuildWaves = 4;                     // waves per workgroup
+constexpr int kBuildWords = 9 * 3 * kBuildSites;   // 16-byte words of a chunk's 63 matrices
+constexpr int kBuildLoads = (kBuildWords + 63) / 64;
+
+// Coalesced loads of one chunk (kBuildSites consecutive sites s0.. of the slice at Ut):
+// word w of the chunk's own matrices is word w % 27 of site w / 27 (its spatial links, the
+// t link skipped); word w of the neighbour matrices is word w % 9 of the neighbour link
+// U_mu(x + mu^) of pair p = w / 9 (site p / 3, mu = p % 3), whose site index lane p computes
+// and shares by a shuffle.  Sites past the slice end read the last site.
+template <bool ONE>
+__device__ __forceinline__ void build_load(const v2d* __restrict__ Ut, int s0, int V3, int Lx, int Ly, int Lz,
+                                           int lane, v2d (&va)[kBuildLoads], v2d (&vb)[kBuildLoads]) {
+  const int lp = min(lane, 3 * kBuildSites - 1);
+  const int ps = lp / 3, mu = lp - 3 * ps;
+  const int ii = min(s0 + ps, V3 - 1);
+  const int x = ii % Lx, yz = ii / Lx, y = yz % Ly, z = yz / Ly;
+  const int xp = x + 1 == Lx ? 0 : x + 1, yp = y + 1 == Ly ? 0 : y + 1, zp = z + 1 == Lz ? 0 : z + 1;
+  const int nbl = mu == 0 ? (z * Ly + y) * Lx + xp : mu == 1 ? (z * Ly + yp) * Lx + x : (zp * Ly + y) * Lx + x;
 #pragma unroll
-  for (int q = 0; q < 9; q++) a[q] = A[q];
-  double c[18];
-  if (one) {
+  for (int k = 0; k < kBuildLoads; k++) {
+    const int w = min(lane + 64 * k, kBuildWords - 1);
+    const int site = w / 27, q = w - 27 * site;
+    va[k] = Ut[(int64_t)min(s0 + site, V3 - 1) * 36 + q];
+    if constexpr (!ONE) {
+      const int p = w / 9, jw = w - 9 * p;
+      vb[k] = Ut[(int64_t)__shfl(nbl, p, 64) * 36 + (p - 3 * (p / 3)) * 9 + jw];
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// W_mu(x) = U_mu(x) U_mu(x + mu^) in FP64, stored in format P; with the ONE bit in P the
+// links U_mu(x) themselves (a one-link field).  A chunk of 21 consecutive sites is one
+// wave's work, one (site, mu) pair per lane, mu fastest.  A lane's own matrix and its
+// neighbour's are 144-byte runs 576 bytes apart (the caller's layout interleaves the t
+// links): lanes loading them directly would each touch their own cache lines, and the
+// texture addresser rather than HBM would bound the kernel.  So the wave loads the chunk's
+// words with consecutive lanes on consecutive words (build_load), writes them to its part
+// of LDS, and each lane reads its two matrices back.  A workgroup takes four consecutive
+// chunks of one slice.
+template <int P>
+__global__ __launch_bounds__(64 * kBuildWaves) void build_twolinks_kernel(const double2* __restrict__ U, int Lx, int Ly,
+                                                                           int Lz, int t_first, int slot_first,
+                                                                           int per_slice, char* __restrict__ W,
+                                                                           int64_t Vp) {
+  constexpr bool one = is_one(P);
+  __shared__ v2d lds[kBuildWaves][2][kBuildLoads * 64];
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int V3 = Lx * Ly * Lz;
+  const int sl = (int)blockIdx.x / per_slice;
+  const int s0 = (((int)blockIdx.x - sl * per_slice) * kBuildWaves + wave) * kBuildSites;
+  if (s0 >= V3) return;   // wave-uniform: a slice's last workgroup may have idle waves
+  v2d(&own)[kBuildLoads * 64] = lds[wave][0];
+  v2d(&nbr)[kBuildLoads * 64] = lds[wave][1];
+  {
+    v2d va[kBuildLoads], vb[kBuildLoads];
+    build_load<one>(reinterpret_cast<const v2d*>(U) + (int64_t)(t_first + sl) * V3 * 36, s0, V3, Lx, Ly, Lz, lane,
+                    va, vb);
+#pragma unroll
+    for (int k = 0; k < kBuildLoads; k++) {
+      own[lane + 64 * k] = va[k];
+      if constexpr (!one) nbr[lane + 64 * k] = vb[k];
+    }
+  }
+  wave_sync_lds();   // each lane reads words other lanes of its wave wrote
+  const int lp = min(lane, 3 * kBuildSites - 1);
+  const int ps = lp / 3, mu = lp - 3 * ps;
+  if (lane >= 3 * kBuildSites || s0 + ps >= V3) return;
+  v2d a[9];
+#pragma unroll
+  for (int q = 0; q < 9; q++) a[q] = own[9 * lp + q];
+  double m[18];
+  if constexpr (one) {
 #pragma unroll
     for (int q = 0; q < 9; q++) {
-      c[2 * q] = a[q].x;
-      c[2 * q + 1] = a[q].y;
+      m[2 * q] = a[q].x;
+      m[2 * q + 1] = a[q].y;
     }
-    Fmt<P>::store_w(Wm, Vp, i, c);
-    return;
-  }
-  const double2* B = U + ((base + nb) * 4 + mu) * 9;
-  double2 b[9];
+  } else {
+    v2d bq[9];
 #pragma unroll
-  for (int q = 0; q < 9; q++) b[q] = B[q];
+    for (int q = 0; q < 9; q++) bq[q] = nbr[9 * lp + q];
 #pragma unroll
-  for (int r = 0; r < 3; r++)
+    for (int r = 0; r < 3; r++)
 #pragma unroll
-    for (int s = 0; s < 3; s++) {
-      double re = 0.0, im = 0.0;
+      for (int t = 0; t < 3; t++) {
+        double re = 0.0, im = 0.0;
 #pragma unroll
-      for (int q = 0; q < 3; q++) {
-        const double2 p = a[3 * r + q], w = b[3 * q + s];
-        re = fma_(p.x, w.x, re);
-        re = fma_(-p.y, w.y, re);
-        im = fma_(p.x, w.y, im);
-        im = fma_(p.y, w.x, im);
+        for (int q = 0; q < 3; q++) {
+          const v2d pa = a[3 * r + q], pb = bq[3 * q + t];
+          re = fma_(pa.x, pb.x, re);
+          re = fma_(-pa.y, pb.y, re);
+          im = fma_(pa.x, pb.y, im);
+          im = fma_(pa.y, pb.x, im);
+        }
+        m[2 * (3 * r + t)] = re;
+        m[2 * (3 * r + t) + 1] = im;
       }
-      c[2 * (3 * r + s)] = re;
-      c[2 * (3 * r + s) + 1] = im;
-    }
-  Fmt<P>::store_w(Wm, Vp, i, c);
+  }
+  char* const Wm = W + ((int64_t)(slot_first + sl) * 3 + mu) * Vp * kWBytes[P];
+  Fmt<P>::store_w(Wm, Vp, s0 + ps, m);
 }
 
 // ------------------------------------------------------------------ pack / unpack
@@ -235,6 +282,29 @@ __global__ __launch_bounds__(kRedBlock) void site_norm_kernel(const char* __rest
   out[fr.out_off + i] = sqrt(s);
 }
 
+// Streaming probe: out[i] = sum of the n_in input planes' word i (FP32 adds), n_in reads
+// per write, loads cached or nontemporal (NTL), stores cached or nontemporal (NTS).  Each
+// thread handles four words per pass of a grid-stride loop.
+template <bool NTL, bool NTS>
+__global__ __launch_bounds__(256) void stream_kernel(const v4f* __restrict__ in, int n_in, v4f* __restrict__ out,
+                                                      int64_t n_words) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n_words; i0 += 4 * stride) {
+    v4f acc[4] = {};
+    for (int p = 0; p < n_in; p++) {
+      const v4f* src = in + (int64_t)p * n_words;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int64_t i = min(i0 + u * stride, n_words - 1);
+        acc[u] += NTL ? __builtin_nontemporal_load(src + i) : src[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (i0 + u * stride < n_words) put<NTS>(out + i0 + u * stride, acc[u]);
+  }
+}
+
 __global__ void compare_kernel(const uint4* __restrict__ a, const uint4* __restrict__ b, int64_t n16,
                                const unsigned char* __restrict__ ta, const unsigned char* __restrict__ tb,
                                int64_t ntail, int* __restrict__ flag) {
@@ -280,14 +350,17 @@ hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first
   const int64_t V3 = (int64_t)L[0] * L[1] * L[2];
   const int64_t Vp = padded_sites(V3);
   if (n_slices <= 0 || V3 <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((3 * V3 + 255) / 256), (unsigned)n_slices);
+  if (code < 0 || code > (BF16 | W12 | ONE)) return hipErrorInvalidValue;
+  // workgroups per slice: a workgroup never spans two slices
+  const int64_t per_slice = (V3 + kBuildSites * kBuildWaves - 1) / (kBuildSites * kBuildWaves);
+  const int64_t blocks = per_slice * n_slices;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
   const double2* u = static_cast<const double2*>(U);
   char* w = static_cast<char*>(W);
-  if (code < 0 || code > (BF16 | W12 | ONE)) return hipErrorInvalidValue;
-  const int one = is_one(code) ? 1 : 0;
 #define TL_BUILD(C) \
-  case C: build_twolinks_kernel<C><<<grid, 256, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, w, Vp, one); break;
-  switch (code & 7) {
+  case C: build_twolinks_kernel<C><<<grid, 64 * kBuildWaves, 0, s>>>(u, L[0], L[1], L[2], t_first, slot_first, (int)per_slice, w, Vp); break;
+  switch (code) {
     TL_BUILD(F64)
     TL_BUILD(F32)
     TL_BUILD(F16S)
@@ -296,6 +369,14 @@ hipError_t launch_build(int code, const void* U, const int32_t L[4], int t_first
     TL_BUILD(F32 | W12)
     TL_BUILD(F16S | W12)
     TL_BUILD(BF16 | W12)
+    TL_BUILD(F64 | ONE)
+    TL_BUILD(F32 | ONE)
+    TL_BUILD(F16S | ONE)
+    TL_BUILD(BF16 | ONE)
+    TL_BUILD(F64 | W12 | ONE)
+    TL_BUILD(F32 | W12 | ONE)
+    TL_BUILD(F16S | W12 | ONE)
+    TL_BUILD(BF16 | W12 | ONE)
     default: return hipErrorInvalidValue;
   }
 #undef TL_BUILD
@@ -411,6 +492,19 @@ hipError_t launch_reduce_flat(int kind, const void* psi, const void* phi, int64_
                               double* partials, double* out, hipStream_t s) {
   return reduce_with(kind, -1, static_cast<const char*>(psi), static_cast<const char*>(phi), FlatFields{n_sites},
                      n_rhs, n_sites, partials, out, s);
+}
+
+hipError_t launch_stream(void* buf, int64_t n_words, int n_in, int kinds, int grid, hipStream_t s) {
+  if (n_words <= 0 || n_in < 1 || grid < 1) return hipErrorInvalidValue;
+  const v4f* in = static_cast<const v4f*>(buf);
+  v4f* out = static_cast<v4f*>(buf) + (int64_t)n_in * n_words;
+  switch (kinds & 3) {
+    case 0: stream_kernel<false, false><<<grid, 256, 0, s>>>(in, n_in, out, n_words); break;
+    case 1: stream_kernel<true, false><<<grid, 256, 0, s>>>(in, n_in, out, n_words); break;
+    case 2: stream_kernel<false, true><<<grid, 256, 0, s>>>(in, n_in, out, n_words); break;
+    default: stream_kernel<true, true><<<grid, 256, 0, s>>>(in, n_in, out, n_words); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_compare(const char* a, const char* b, int64_t n_bytes, int* flag, hipStream_t s) {

@@ -1070,6 +1070,42 @@ int tl_plan_time(tl_plan* p, int reps, double* ms_per_step) {
   }
 }
 
+int tl_stream_time(tl_ctx* c, void* buf, int64_t bytes, int n_in, int kinds, int grid, int reps, double* ms) {
+  try {
+    if (!c) return TL_ERR_ARG;
+    if (!buf || !ms || reps < 1) return fail(c, TL_ERR_ARG, "need a buffer, an output pointer and reps >= 1");
+    if (n_in < 1 || n_in > 16) return fail(c, TL_ERR_ARG, "n_in = %d outside [1, 16]", n_in);
+    if (kinds < 0 || kinds > 3 || grid < 0) return fail(c, TL_ERR_ARG, "bad kinds %d or grid %d", kinds, grid);
+    if (reinterpret_cast<uintptr_t>(buf) % 256) return fail(c, TL_ERR_ARG, "buffer not 256-byte aligned");
+    const int64_t n_words = bytes / 16 / (n_in + 1);
+    if (n_words < 1) return fail(c, TL_ERR_ARG, "buffer of %lld bytes too small", (long long)bytes);
+    TL_TRY(need_device(c));
+    TL_ON_DEVICE(c);
+    const int g = grid > 0 ? grid : 16 * std::max(c->n_cu, 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(c, TL_ERR_HIP, "hipEventCreate failed");
+    }
+    int rc = launch(c, "stream", [&] { return tl::launch_stream(buf, n_words, n_in, kinds, g, c->stream); });
+    if (rc == TL_OK) (void)hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps && rc == TL_OK; k++)
+      rc = launch(c, "stream", [&] { return tl::launch_stream(buf, n_words, n_in, kinds, g, c->stream); });
+    float t = 0.0f;
+    if (rc == TL_OK) {
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        rc = fail(c, TL_ERR_HIP, "event timing failed");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == TL_OK) *ms = t / reps;
+    return rc;
+  } catch (...) {
+    return host_failure(c);
+  }
+}
+
 int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
   try {
     if (!p || !info) return TL_ERR_ARG;

@@ -219,6 +219,19 @@ def test_reduce_noalloc_validation(lib, hctx):
     assert f(hctx, 2, 4096 * 65, 1024, FAKE, None, out) == -4      # site norms need no partial sums
 
 
+def test_stream_probe_validation(lib, hctx):
+    ms = ctypes.c_double()
+    f = lib.tl_stream_time
+    buf = ctypes.c_void_p(0x100000)
+    assert f(hctx, buf, 1 << 20, 4, 2, 0, 3, ctypes.byref(ms)) == -4          # valid: no device
+    assert f(hctx, buf, 1 << 20, 0, 2, 0, 3, ctypes.byref(ms)) == -1          # no input plane
+    assert f(hctx, buf, 1 << 20, 4, 4, 0, 3, ctypes.byref(ms)) == -1          # unknown kinds
+    assert f(hctx, buf, 1 << 20, 4, 2, 0, 0, ctypes.byref(ms)) == -1          # reps
+    assert f(hctx, ctypes.c_void_p(0x100010), 1 << 20, 4, 2, 0, 3, ctypes.byref(ms)) == -1   # alignment
+    assert f(hctx, buf, 64, 4, 2, 0, 3, ctypes.byref(ms)) == -1               # too small
+    assert f(hctx, buf, 1 << 20, 4, 2, 0, 3, None) == -1
+
+
 def test_null_context(lib):
     g = geom(4, 4, 4, 4)
     assert lib.tl_build_twolinks(None, ctypes.byref(g), FAKE, None, 0, 1, FAKE) == -1

@@ -184,6 +184,20 @@ def test_side_stream_and_second_context(ctx, orc, torch):
         c2.close()
 
 
+@pytest.mark.parametrize("kinds", [0, 1, 2, 3])
+def test_stream_probe_sums_planes(ctx, torch, kinds):
+    """The streaming probe writes its last plane as the sum of the others (any load/store kind)."""
+    n_in, words = 4, 10000 + 37
+    vals = torch.arange(n_in * words * 4, dtype=torch.float32, device="cuda").remainder_(97.0)
+    buf = torch.zeros((n_in + 1) * words * 16 + 48, dtype=torch.uint8, device="cuda")
+    buf[: n_in * words * 16].view(torch.float32).copy_(vals)
+    ms = ctx.stream_time(buf, n_in=n_in, kinds=kinds, grid=7, reps=2)
+    torch.cuda.synchronize()
+    assert ms > 0.0
+    planes = buf[: (n_in + 1) * words * 16].view(torch.float32).view(n_in + 1, words * 4)
+    assert torch.equal(planes[n_in], planes[:n_in].sum(dim=0))
+
+
 def test_stream_switch_orders_scratch(orc, torch):
     """tl_set_stream between two Laplacians of different shapes: the second call reuses the
     context scratch (its table upload and pack) while the first may still run on the old
