@@ -110,6 +110,14 @@ enum {
 
 typedef struct { int32_t L[4]; } tl_geom;   /* Lx, Ly, Lz, Lt */
 
+/* Counters of one context (filled by tl_get_stats). */
+typedef struct {
+    int64_t graphs_captured;   /* HIP graphs captured by the context's plans */
+    int64_t tune_sweeps;       /* autotuning sweeps run (TL_AUTOTUNE with no cached result) */
+    int64_t tune_hits;         /* plans whose tiling came from the tuning cache (memory or TL_TUNE_CACHE) */
+    int64_t smear_plan_hits;   /* tl_smear(TL_GRAPH) calls served by a plan kept from an earlier call */
+} tl_ctx_stats;
+
 typedef struct tl_ctx tl_ctx;
 typedef struct tl_plan tl_plan;
 
@@ -154,6 +162,11 @@ int tl_version(void);
  *   TL_LOG=1                         print autotuning candidates to stderr
  *   TL_FAULT=alloc|launch            make internal allocations or launches fail
  *                                    (read at tl_create; exercises error paths)
+ *   TL_TUNE_CACHE=<path>             a JSON file of autotuning results: read at tl_create,
+ *                                    rewritten after every sweep, so that a later process
+ *                                    skips the sweep for batch shapes already tuned (keys name
+ *                                    the GPU architecture, precision, group width, launch mode
+ *                                    and every group's extents and RHS count)
  */
 
 /*
@@ -178,6 +191,8 @@ int tl_set_stream(tl_ctx *ctx, void *stream);
 int tl_sync(tl_ctx *ctx);
 /* Message of the last failing call on ctx (ctx = NULL: last failure of tl_create on this thread). */
 const char *tl_last_error(const tl_ctx *ctx);
+/* The context's counters (TL_ERR_ARG for NULL arguments). */
+int tl_get_stats(const tl_ctx *ctx, tl_ctx_stats *out);
 
 /* ------------------------------------------------------------------ sizes */
 
@@ -231,8 +246,14 @@ int tl_laplacian(tl_ctx *ctx, const tl_geom *g, const void *W, const int32_t *w_
  * Smearing of eq. tlSmear, psi <- (1 + (sigma/n) Lap)^n psi with n = n_steps,
  * applied in place to every right-hand side of every job on its own slice.
  * Jobs may have different geometries (uneven batch).  Equivalent to
- * tl_plan_create + load + run + store + destroy.  Requires n_steps >= 0,
- * finite sigma with 0 <= sigma/n_steps <= 2/3 (the step is then a contraction).
+ * tl_plan_create + load + run + store + destroy, except with TL_GRAPH: the
+ * context then keeps the plan (resident buffers, work list, tiling, captured
+ * graph) of its 4 most recent distinct calls, keyed by everything the call
+ * passes (device pointers, geometries, slice lists, n, sigma, precision,
+ * flags), and a repeated call replays the kept graph without capturing; the
+ * kept plans hold device memory until they are displaced or tl_destroy.
+ * Requires n_steps >= 0, finite sigma with 0 <= sigma/n_steps <= 2/3 (the step
+ * is then a contraction).
  */
 int tl_smear(tl_ctx *ctx, const tl_job *jobs, int n_jobs, int n_steps, double sigma,
              int prec, unsigned flags);

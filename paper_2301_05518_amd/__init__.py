@@ -147,6 +147,12 @@ class Context:
     def sync(self):
         self._check(self.lib.tl_sync(self.h))
 
+    def stats(self) -> dict:
+        """The context's counters: graphs captured, tuning sweeps and cache hits, kept tl_smear plans reused."""
+        st = _lib.CtxStats()
+        self._check(self.lib.tl_get_stats(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
     def set_stream(self, stream):
         """Queue later work on a torch stream of the context's device (tl_set_stream: the new
         stream first waits for what the context queued on the old one)."""

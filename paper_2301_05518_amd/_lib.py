@@ -25,7 +25,7 @@ EXPORTS = [
     "tl_version", "tl_create", "tl_destroy", "tl_set_stream", "tl_sync", "tl_last_error",
     "tl_check_geom", "tl_twolinks_bytes", "tl_build_twolinks", "tl_pack_links", "tl_laplacian", "tl_smear",
     "tl_plan_create", "tl_plan_load", "tl_plan_run", "tl_plan_store", "tl_plan_reduce",
-    "tl_plan_time", "tl_plan_get_info", "tl_plan_destroy", "tl_reduce", "tl_reduce_noalloc", "tl_stream_time",
+    "tl_plan_time", "tl_plan_get_info", "tl_plan_destroy", "tl_reduce", "tl_reduce_noalloc", "tl_stream_time", "tl_get_stats",
 ]
 
 
@@ -43,6 +43,11 @@ class Job(ctypes.Structure):
         ("t_of_rhs", ctypes.POINTER(ctypes.c_int32)),
         ("psi", ctypes.c_void_p),
     ]
+
+
+class CtxStats(ctypes.Structure):
+    _fields_ = [("graphs_captured", ctypes.c_int64), ("tune_sweeps", ctypes.c_int64),
+                ("tune_hits", ctypes.c_int64), ("smear_plan_hits", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -99,6 +104,7 @@ def load() -> ctypes.CDLL:
         "tl_reduce": (i32, [vp, i32, i64, i32, vp, vp, vp]),
         "tl_reduce_noalloc": (i32, [vp, i32, i64, i32, vp, vp, vp]),
         "tl_stream_time": (i32, [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(dbl)]),
+        "tl_get_stats": (i32, [vp, ctypes.POINTER(CtxStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -9,10 +9,16 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <list>
 #include <map>
 #include <new>
+#include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
+
+#include <unistd.h>
 
 #include "tl_internal.h"
 #include "twolink.h"
@@ -40,6 +46,9 @@ struct tl_ctx {
   double* noalloc = nullptr;  // this device's fixed partial-sum area of tl_reduce_noalloc
   std::string noalloc_err;    // why it is missing (lookup failed at tl_create)
   std::map<std::string, StepConfig> tune;  // tuned step configurations by workload key
+  std::string tune_file;                   // TL_TUNE_CACHE: tuning results persisted across processes
+  std::list<std::pair<std::string, tl_plan*>> smear_plans;   // tl_smear(TL_GRAPH) plans, most recent first
+  tl_ctx_stats stats{};
 };
 
 namespace {
@@ -209,6 +218,53 @@ void step_coeffs(bool one, int n_steps, double sigma, double* alpha, double* bet
 
 // Largest sigma/n for which every step factor lies in [-1, 1] (a contraction for unitary links).
 double max_step(bool one) { return one ? 1.0 / 6.0 : 2.0 / 3.0; }
+
+// Tuning cache file (TL_TUNE_CACHE): a JSON object {"<workload key>": "variant,block,tz,grid,nt,flip", ...}.
+// The keys (architecture, precision code, group width, launch mode, each group's dims and RHS)
+// hold no quote or backslash, so the file is read and written with plain string handling;
+// a missing, unreadable or malformed file is an empty cache.
+void tune_file_load(tl_ctx* c) {
+  std::ifstream in(c->tune_file);
+  if (!in) return;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = 0;
+  while (true) {
+    const size_t k0 = t.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = t.find('"', k0 + 1);
+    const size_t v0 = k1 == std::string::npos ? k1 : t.find('"', k1 + 1);
+    const size_t v1 = v0 == std::string::npos ? v0 : t.find('"', v0 + 1);
+    if (v1 == std::string::npos) break;
+    StepConfig cfg{};
+    const std::string val = t.substr(v0 + 1, v1 - v0 - 1);
+    if (sscanf(val.c_str(), "%d,%d,%d,%d,%d,%d", &cfg.variant, &cfg.block, &cfg.tz, &cfg.grid, &cfg.nt, &cfg.flip) == 6 &&
+        cfg.variant >= 0 && cfg.variant <= 7 && cfg.block >= 64 && cfg.block <= 512 && cfg.block % 64 == 0 &&
+        cfg.tz >= 1 && (cfg.nt == 0 || cfg.nt == 1) && (cfg.flip == 0 || cfg.flip == 1))
+      c->tune[t.substr(k0 + 1, k1 - k0 - 1)] = cfg;
+    pos = v1 + 1;
+  }
+}
+
+// Rewrite the whole file (a temporary then a rename, so a reader never sees half a file).
+void tune_file_save(const tl_ctx* c) {
+  const std::string tmp = c->tune_file + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream out(tmp);
+    if (!out) return;
+    out << "{\n";
+    size_t k = 0;
+    for (const auto& kv : c->tune) {
+      const StepConfig& g = kv.second;
+      out << "  \"" << kv.first << "\": \"" << g.variant << "," << g.block << "," << g.tz << "," << g.grid << ","
+          << g.nt << "," << g.flip << "\"" << (++k < c->tune.size() ? ",\n" : "\n");
+    }
+    out << "}\n";
+    if (!out) return;
+  }
+  (void)std::rename(tmp.c_str(), c->tune_file.c_str());
+}
 
 }  // namespace
 
@@ -392,8 +448,10 @@ int plan_autotune(tl_plan* p) {
   auto hit = c->tune.find(key);
   if (hit != c->tune.end()) {
     p->cfg = hit->second;
+    c->stats.tune_hits++;
     return plan_upload_groups(p, p->cfg);
   }
+  c->stats.tune_sweeps++;
   std::vector<StepConfig> cands;
   const int cu = std::max(c->n_cu, 1);
   for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
@@ -475,6 +533,7 @@ int plan_autotune(tl_plan* p) {
   if (rc != TL_OK) return rc;
   p->cfg = best_cfg;
   c->tune[key] = best_cfg;
+  if (!c->tune_file.empty()) tune_file_save(c);
   return plan_upload_groups(p, p->cfg);
 }
 
@@ -524,6 +583,7 @@ int plan_capture(tl_plan* p, int parity) {
   if (rc == TL_OK) {
     hipError_t e = hipGraphInstantiate(&p->graph[parity], graph, nullptr, nullptr, 0);
     if (e != hipSuccess) rc = fail(c, TL_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    else c->stats.graphs_captured++;
   }
   if (graph) (void)hipGraphDestroy(graph);
   (void)hipStreamDestroy(cs);
@@ -561,6 +621,11 @@ int tl_create(tl_ctx** out, int device, void* stream) {
     if (!c) return fail(nullptr, TL_ERR_NOMEM, "host allocation failed");
     const char* lg = getenv("TL_LOG");
     c->log = lg && lg[0] == '1';
+    const char* tf = getenv("TL_TUNE_CACHE");
+    if (tf && tf[0]) {
+      c->tune_file = tf;
+      tune_file_load(c);
+    }
     const char* fl = getenv("TL_FAULT");
     if (fl) {
       c->fault_alloc = strcmp(fl, "alloc") == 0;
@@ -622,6 +687,8 @@ int tl_create(tl_ctx** out, int device, void* stream) {
 int tl_destroy(tl_ctx* c) {
   try {
     if (!c) return TL_ERR_ARG;
+    for (auto& sp : c->smear_plans) plan_free(sp.second);
+    c->smear_plans.clear();
     if (c->device >= 0) {
       DeviceGuard dg(c->device);   // teardown goes on even if the switch fails
       (void)hipStreamSynchronize(c->stream);
@@ -1133,19 +1200,80 @@ int tl_plan_destroy(tl_plan* p) {
   }
 }
 
+namespace {
+
+constexpr size_t kSmearPlans = 4;   // tl_smear(TL_GRAPH) plans a context keeps
+
+// Everything a tl_smear plan depends on: the job list (geometries, device pointers, slice lists,
+// RHS slices), n, sigma (its bits), the precision code and the flags.
+std::string smear_signature(const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags) {
+  std::string k;
+  char buf[128];
+  uint64_t sb;
+  std::memcpy(&sb, &sigma, sizeof sb);
+  snprintf(buf, sizeof buf, "n%d|s%llx|p%d|f%u|j%d", n_steps, (unsigned long long)sb, prec, flags, n_jobs);
+  k += buf;
+  for (int j = 0; j < n_jobs; j++) {
+    const tl_job& b = jobs[j];
+    snprintf(buf, sizeof buf, "|%d,%d,%d,%d:%p:%p:%d:", b.g.L[0], b.g.L[1], b.g.L[2], b.g.L[3], b.W, b.psi, b.n_rhs);
+    k += buf;
+    for (int r = 0; r < b.n_rhs; r++) k += std::to_string(b.t_of_rhs[r]) + ",";
+    if (b.w_slices) {
+      k += "w";
+      for (int i = 0; i < b.n_w_slices; i++) k += std::to_string(b.w_slices[i]) + ",";
+    }
+  }
+  return k;
+}
+
+}  // namespace
+
 int tl_smear(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags) {
   try {
     if (!c) return TL_ERR_ARG;
+    // the signature reads the jobs' host arrays: malformed jobs are not kept (tl_plan_create refuses them)
+    bool keep = (flags & TL_GRAPH) && jobs && n_jobs >= 1;
+    for (int j = 0; keep && j < n_jobs; j++)
+      if (jobs[j].n_rhs < 1 || !jobs[j].t_of_rhs || (jobs[j].w_slices && jobs[j].n_w_slices < 1)) keep = false;
+    std::string sig;
+    if (keep) {
+      sig = smear_signature(jobs, n_jobs, n_steps, sigma, prec, flags);
+      for (auto it = c->smear_plans.begin(); it != c->smear_plans.end(); ++it) {
+        if (it->first != sig) continue;
+        c->smear_plans.splice(c->smear_plans.begin(), c->smear_plans, it);   // most recent first
+        tl_plan* p = c->smear_plans.front().second;
+        c->stats.smear_plan_hits++;
+        p->cur = 0;   // the sources are packed afresh, into the buffer whose graph was captured first
+        int rc = tl_plan_load(p);
+        if (rc == TL_OK) rc = tl_plan_run(p);
+        if (rc == TL_OK) rc = tl_plan_store(p);
+        return rc;
+      }
+    }
     tl_plan* p = nullptr;
     TL_TRY(tl_plan_create(c, jobs, n_jobs, n_steps, sigma, prec, flags, &p));
     int rc = tl_plan_load(p);
     if (rc == TL_OK) rc = tl_plan_run(p);
     if (rc == TL_OK) rc = tl_plan_store(p);
-    plan_free(p);   // waits for the queued work before releasing the resident buffers
+    if (!keep || rc != TL_OK) {
+      plan_free(p);   // waits for the queued work before releasing the resident buffers
+      return rc;
+    }
+    c->smear_plans.emplace_front(std::move(sig), p);
+    if (c->smear_plans.size() > kSmearPlans) {
+      plan_free(c->smear_plans.back().second);
+      c->smear_plans.pop_back();
+    }
     return rc;
   } catch (...) {
     return host_failure(c);
   }
+}
+
+int tl_get_stats(const tl_ctx* c, tl_ctx_stats* out) {
+  if (!c || !out) return TL_ERR_ARG;
+  *out = c->stats;
+  return TL_OK;
 }
 
 namespace {

@@ -91,6 +91,10 @@ int main() {
   expect(tl_stream_time(c, fake, 1 << 20, 4, 2, 0, 3, &ms), TL_ERR_DEVICE, "stream valid");
   expect(tl_stream_time(c, fake, 64, 4, 2, 0, 3, &ms), TL_ERR_ARG, "stream too small");
 
+  tl_ctx_stats st;
+  expect(tl_get_stats(c, &st), TL_OK, "stats");
+  expect((int)(st.graphs_captured + st.tune_sweeps + st.tune_hits + st.smear_plan_hits), 0, "no device work counted");
+  expect(tl_get_stats(c, nullptr), TL_ERR_ARG, "stats NULL");
   expect(tl_set_stream(c, nullptr), TL_OK, "set stream on a host-only context");
   expect(tl_sync(c), TL_ERR_DEVICE, "sync host-only");
   expect(std::strlen(tl_last_error(c)) > 0 ? 0 : 1, 0, "error message");
