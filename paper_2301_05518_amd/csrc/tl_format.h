@@ -45,28 +45,31 @@ __device__ __forceinline__ double fma_(double a, double b, double c) { return __
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
-__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
 
 __device__ __forceinline__ float h_to_f32(uint32_t bits16) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
 }
 
-__device__ __forceinline__ uint32_t f32_to_h(float f) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
-}
 
 // FP64 -> half in one rounding (to nearest even).
 __device__ __forceinline__ uint32_t f64_to_h(double d) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)d);
 }
 
-__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) { return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16); }
-__device__ __forceinline__ uint32_t pack_h(float lo, float hi) { return f32_to_h(lo) | (f32_to_h(hi) << 16); }
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to bf16 (round to nearest even) in one word, lo in bits 0-15: one
+// v_cvt_pk_bf16_f32 on gfx950.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){lo, hi}, v2bf));
+}
+// Two FP32 values to IEEE half (round to nearest even) in one word: one v_cvt_pk_f16_f32.
+__device__ __forceinline__ uint32_t pack_h(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){lo, hi}, h2));
+}
 // Two-link reals (FP64): half in one rounding; bf16 through FP32.
 __device__ __forceinline__ uint32_t pack_h_d(double lo, double hi) { return f64_to_h(lo) | (f64_to_h(hi) << 16); }
 __device__ __forceinline__ uint32_t pack_bf16_d(double lo, double hi) { return pack_bf16((float)lo, (float)hi); }
