@@ -585,14 +585,16 @@ __global__ __launch_bounds__(256) void step_zfront(const StepGroup* __restrict__
 // one direction's loads (two two-links and 2R colour vectors) are live at a
 // time.  Fewer registers allow more waves per SIMD, which hide the memory
 // latency of each direction and overlap one wave's arithmetic with the
-// others' loads.
+// others' loads.  Fields are addressed through per-plane base pointers (uniform
+// across the workgroup) plus 32-bit site offsets, so a load costs one offset
+// rather than a 64-bit address computation.
 template <int P, int R, bool NT>
 __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__ groups, int n_groups,
                                                    int tile_base, int n_tiles, int tz, int rev,
                                                    const char* __restrict__ in, char* __restrict__ out,
                                                    typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
-  using F = Fmt<P>;
-  using real = typename F::real;
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
   constexpr int D = hop_of(P);   // hop distance: 2 (two-link field), 1 (one-link field)
   const TileSweep sw = xcd_sweep(n_tiles, rev);
   for (int m = 0; m < sw.n; m++) {
@@ -611,21 +613,21 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
     const int xf = y * Lx + wrap_step(x, D, Lx), xb = y * Lx + wrap_step(x, -D, Lx);
     const int yf = wrap_step(y, D, Ly) * Lx + x, yb = wrap_step(y, -D, Ly) * Lx + x;
     const int nr = g.nr;
-    const char* pin[R];
-    char* pout[R];
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
-      pin[r] = in + o;
-      pout[r] = out + o;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
     }
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, Lz);
     for (int z = z0; z < z1; z++) {
-      const int64_t zo = (int64_t)z * LxLy;
-      const int64_t zf = (int64_t)wrap_step(z, D, Lz) * LxLy + xy;
-      const int64_t zb = (int64_t)wrap_step(z, -D, Lz) * LxLy + xy;
-      const int64_t site = zo + xy;
+      const uint32_t zo = (uint32_t)(z * LxLy);
+      const uint32_t zf = (uint32_t)(wrap_sel(z + D, Lz) * LxLy + xy);
+      const uint32_t zb = (uint32_t)(wrap_sel(z - D, Lz) * LxLy + xy);
+      const uint32_t site = zo + (uint32_t)xy;
       real acc[R][6];
 #pragma unroll
       for (int r = 0; r < R; r++)
@@ -633,32 +635,33 @@ __global__ __launch_bounds__(256) void step_rolled(const StepGroup* __restrict__
         for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
 #pragma unroll 1
       for (int mu = 0; mu < 3; mu++) {
-        const char* Wm = g.W + mu * g.w_mu_stride;
-        const int64_t f = mu == 0 ? zo + xf : (mu == 1 ? zo + yf : zf);
-        const int64_t b = mu == 0 ? zo + xb : (mu == 1 ? zo + yb : zb);
-        real m[18];
-        F::load_w(Wm, Vp, site, m);
+        const char* wp[PL::NW];
+        PL::w(g.W + mu * g.w_mu_stride, Vp, wp);
+        const uint32_t f = mu == 0 ? zo + (uint32_t)xf : (mu == 1 ? zo + (uint32_t)yf : zf);
+        const uint32_t b = mu == 0 ? zo + (uint32_t)xb : (mu == 1 ? zo + (uint32_t)yb : zb);
+        real mtx[18];
+        PL::load_w(wp, site, mtx);
 #pragma unroll
         for (int r = 0; r < R; r++) {
           real v[6];
-          F::load_v(pin[r], Vp, f, v);
-          mv_acc(m, v, acc[r]);
+          PL::load_v(ip[r], f, v);
+          mv_acc(mtx, v, acc[r]);
         }
-        F::load_w(Wm, Vp, b, m);
+        PL::load_w(wp, b, mtx);
 #pragma unroll
         for (int r = 0; r < R; r++) {
           real v[6];
-          F::load_v(pin[r], Vp, b, v);
-          mdv_acc(m, v, acc[r]);
+          PL::load_v(ip[r], b, v);
+          mdv_acc(mtx, v, acc[r]);
         }
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {
         real v[6], o[6];
-        F::load_v(pin[r], Vp, site, v);
+        PL::load_v(ip[r], site, v);
 #pragma unroll
         for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * v[c]);
-        if (r < nr) F::template store_v<real, NT>(pout[r], Vp, site, o);
+        if (r < nr) PL::template store_v<real, NT>(op[r], site, o);
       }
     }
   }
