@@ -343,9 +343,13 @@ def measure_workload(ctx, torch, tl, dev, index, prec, plain=False, passes=5):
     pass_ms = e0.elapsed_time(e1) / passes
     step_ms = plan.time(reps=5)
     info = plan.info()
-    gbs = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
+    # a launch moves bytes_per_step (W once, the input and the output once) for its one or two steps
+    spl = info["steps_per_launch"]
+    launch_ms = step_ms * wl.n_steps / ((wl.n_steps + spl - 1) // spl)
+    gbs = info["bytes_per_step"] / (launch_ms * 1e-3) / 1e9
     rec = {"workload": wl.name, "storage": prec, "rhs": sum(len(ts) for _, _, ts in lats),
-           "step_us": round(step_ms * 1e3, 2), "pass_ms": round(pass_ms, 4),
+           "step_us": round(step_ms * 1e3, 2), "launch_us": round(launch_ms * 1e3, 2), "steps_per_launch": spl,
+           "pass_ms": round(pass_ms, 4),
            "value": wl.rhs_site_updates / (pass_ms * 1e-3),
            "smear_only_rate": info["rhs_sites"] / (step_ms * 1e-3),
            "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -524,9 +528,10 @@ def main():
     # replayed from the graph, gaps between them included); back-to-back replays outside the
     # timed region are reported beside it.
     info = plan.info()
-    launches = max(1, info["launches_per_step"] * wl.n_steps)
+    spl = info["steps_per_launch"]   # 2: each launch runs two steps (W and the input read once)
+    launches = max(1, info["launches_per_step"] * ((wl.n_steps + spl - 1) // spl))
     step_ms = sum(a.elapsed_time(b) for a, b in run_events) / len(run_events) / launches
-    isolated_ms = plan.time(reps=3)
+    isolated_ms = plan.time(reps=3) * wl.n_steps / launches
     achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
     key = workload_key(args)
     tile = ",".join(str(info[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))
@@ -534,7 +539,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
-                           "step_zpipe"][info["variant"]],
+                           "step_zpipe", "step_fuse2"][info["variant"]],
+                "steps_per_launch": spl,
                 "algorithmic_bytes_per_launch": info["bytes_per_step"],
                 "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
                 "copy_GBs": round(copy_gbs, 1), "ceiling_GBs": ceiling["ceiling_GBs"],

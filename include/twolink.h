@@ -137,13 +137,16 @@ typedef struct {
     int32_t n_groups;          /* RHS groups: RHS of one slice that share each W load */
     int32_t group_width;       /* largest group */
     int32_t n_tiles;           /* work-list entries per step */
-    int32_t variant;           /* step kernel variant (0 direct, 1-3 z-marching, 4 rolled, 5-7 LDS row tiles) */
+    int32_t variant;           /* step kernel variant (0 direct, 1-3 z-marching, 4 rolled, 5-7 LDS row
+                                  tiles, 8 two steps per launch) */
     int32_t block;             /* threads per workgroup */
     int32_t tz;                /* z planes per tile */
     int32_t grid;              /* workgroups per step launch */
     int32_t nt;                /* 1: nontemporal output stores */
     int32_t flip;              /* 1: odd steps run in reversed tile and march order */
     int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN */
+    int32_t steps_per_launch;  /* 2 when each launch runs two steps (variant 8; an odd step count
+                                  ends with one launch of a one-step tiling), else 1 */
     int64_t rhs_sites;         /* sum over RHS of Lx*Ly*Lz */
     double bytes_per_step;     /* algorithmic bytes of one step: W once per group + psi in and out */
     double flops_per_step;     /* 444 per RHS-site-update */
@@ -158,7 +161,9 @@ int tl_version(void);
 /*
  * Environment (read by the library):
  *   TL_TILE="variant,block,tz,grid[,nt[,flip]]"  fix the step tiling of every plan (no tuning);
- *                                    for profiling and sweeps
+ *                                    for profiling and sweeps.  Variant 8 (two steps per
+ *                                    launch) may name the one-step tiling an odd step count
+ *                                    ends with after a ';' (default "0,256,4,0,0,0")
  *   TL_LOG=1                         print autotuning candidates to stderr
  *   TL_FAULT=alloc|launch            make internal allocations or launches fail
  *                                    (read at tl_create; exercises error paths)

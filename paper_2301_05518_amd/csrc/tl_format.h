@@ -436,6 +436,8 @@ template <> struct Planes<F64> : FullW<Planes<F64>, 9> {
 #pragma unroll
     for (int c = 0; c < 3; c++) put<NT>(reinterpret_cast<v2d*>(pl[c] + i * 16u), v2d{(double)v[2 * c], (double)v[2 * c + 1]});
   }
+  // v <- what store_v followed by load_v would give back (the storage rounding, in registers)
+  static __device__ __forceinline__ void round_v(double (&)[6]) {}
 };
 
 template <> struct Planes<F32> : FullW<Planes<F32>, 5> {
@@ -474,6 +476,7 @@ template <> struct Planes<F32> : FullW<Planes<F32>, 5> {
     put<NT>(reinterpret_cast<v4f*>(pl[0] + i * 16u), v4f{(float)v[0], (float)v[1], (float)v[2], (float)v[3]});
     put<NT>(reinterpret_cast<v2f*>(pl[1] + i * 8u), v2f{(float)v[4], (float)v[5]});
   }
+  static __device__ __forceinline__ void round_v(float (&)[6]) {}
 };
 
 template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
@@ -525,6 +528,25 @@ template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
     for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
     put<NT>(reinterpret_cast<v4u*>(pl[0] + i * 16u),
             v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
+  }
+  static __device__ __forceinline__ void round_v(float (&v)[6]) {
+    float f[6];
+    float mx = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      f[c] = v[c];
+      mx = fmaxf(mx, fabsf(f[c]));
+    }
+    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
+    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const uint32_t w = pack_h(f[2 * c], f[2 * c + 1]);
+      v[2 * c] = h_to_f32(w & 0xffffu) * mx;
+      v[2 * c + 1] = h_to_f32(w >> 16) * mx;
+    }
   }
 };
 
@@ -587,6 +609,14 @@ template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
   static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
     put<NT>(reinterpret_cast<v2u*>(pl[0] + i * 8u), v2u{pack_bf16((float)v[0], (float)v[1]), pack_bf16((float)v[2], (float)v[3])});
     put<NT>(reinterpret_cast<uint32_t*>(pl[1] + i * 4u), pack_bf16((float)v[4], (float)v[5]));
+  }
+  static __device__ __forceinline__ void round_v(float (&v)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const uint32_t w = pack_bf16(v[2 * c], v[2 * c + 1]);
+      v[2 * c] = bf16_to_f32(w & 0xffffu);
+      v[2 * c + 1] = bf16_to_f32(w >> 16);
+    }
   }
 };
 

@@ -62,6 +62,10 @@ struct StepConfig {
                  //    in-plane two-links are loaded before the LDS barrier)
                  // 7: as 6, software-pipelined: each plane step issues the next step's
                  //    loads into the registers its own arithmetic has just freed
+                 // 8: two steps per launch: tiles of k rows of one y chain (rows y, y+2, ...),
+                 //    the first step also on one chain row beyond each side, its result
+                 //    kept in LDS for the second (an odd step count ends with one launch
+                 //    of a one-step tiling)
   int block;     // threads per workgroup (xy sites per tile; variants 5-7: an upper bound)
   int tz;        // z planes per tile
   int grid;      // workgroups; <= 0 means one workgroup per tile
@@ -71,6 +75,7 @@ struct StepConfig {
                  // so a step starts on the planes the previous step touched last, which are
                  // still in the Infinity Cache when a step's working set exceeds it
   int rev;       // set per launch: this launch runs reversed
+  int rows64;    // variant 8, set with the work list: every group's rows are 64 sites long
 };
 
 // Rows per tile of variants 5-7 for an Lx x Ly plane and a block size: the largest divisor of Ly
@@ -84,6 +89,22 @@ inline int lds_rows(int Lx, int Ly, int block) {
 // Dynamic LDS bytes variants 5-7 need for a group: two buffers of (rows + 4) rows of R vectors.
 inline int64_t lds_bytes(int code, int R, int Lx, int rows) {
   return 2LL * (rows + 4) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
+}
+
+// Chain rows per tile of variant 8 for an Lx x Ly plane, hop distance D and a block size: the
+// largest k that divides the y chain's length (Ly / 2 for D = 2 and even Ly, else Ly) with
+// (k + 2) * Lx <= block (0 if there is none).
+inline int fuse_rows(int Lx, int Ly, int D, int block) {
+  const int ylen = (D == 2 && !(Ly & 1)) ? Ly / 2 : Ly;
+  for (int k = (block / Lx - 2 < ylen ? block / Lx - 2 : ylen); k >= 1; k--)
+    if (ylen % k == 0) return k;
+  return 0;
+}
+
+// Dynamic LDS bytes variant 8 needs for a group: two input planes of k + 4 rows and two
+// step-one planes of k + 2 rows of R vectors.
+inline int64_t lds_bytes_fuse2(int code, int R, int Lx, int k) {
+  return 2LL * (2 * k + 6) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
 }
 
 // Raise the dynamic-LDS limit of the LDS-staged step kernels (once per device, before any capture).

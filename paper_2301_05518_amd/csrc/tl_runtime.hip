@@ -31,6 +31,13 @@ static_assert(TL_F64 == tl::F64 && TL_F32 == tl::F32 && TL_F16S == tl::F16S && T
 static_assert((TL_W12 & 3) == 0 && (TL_ONELINK & 3) == 0 && TL_W12 != TL_ONELINK,
               "TL_W12 and TL_ONELINK are bits above the precision codes");
 
+// A tuned step tiling: cfg, and when cfg runs two steps per launch (variant 8) the one-step
+// tiling `single` that an odd step count ends with (single.variant < 0: none).
+struct Tuned {
+  StepConfig cfg{0, 256, 4, 0, 0, 0, 0};
+  StepConfig single{-1, 0, 0, 0, 0, 0, 0};
+};
+
 struct tl_ctx {
   int device = -1;
   hipStream_t stream = nullptr;
@@ -45,7 +52,7 @@ struct tl_ctx {
   size_t scratch_bytes = 0;
   double* noalloc = nullptr;  // this device's fixed partial-sum area of tl_reduce_noalloc
   std::string noalloc_err;    // why it is missing (lookup failed at tl_create)
-  std::map<std::string, StepConfig> tune;  // tuned step configurations by workload key
+  std::map<std::string, Tuned> tune;       // tuned step tilings by workload key
   std::string tune_file;                   // TL_TUNE_CACHE: tuning results persisted across processes
   std::list<std::pair<std::string, tl_plan*>> smear_plans;   // tl_smear(TL_GRAPH) plans, most recent first
   tl_ctx_stats stats{};
@@ -219,10 +226,49 @@ void step_coeffs(bool one, int n_steps, double sigma, double* alpha, double* bet
 // Largest sigma/n for which every step factor lies in [-1, 1] (a contraction for unitary links).
 double max_step(bool one) { return one ? 1.0 / 6.0 : 2.0 / 3.0; }
 
-// Tuning cache file (TL_TUNE_CACHE): a JSON object {"<workload key>": "variant,block,tz,grid,nt,flip", ...}.
-// The keys (architecture, precision code, group width, launch mode, each group's dims and RHS)
-// hold no quote or backslash, so the file is read and written with plain string handling;
-// a missing, unreadable or malformed file is an empty cache.
+// A step configuration a cache entry or TL_TILE may name.
+bool valid_cfg(const StepConfig& g) {
+  return g.variant >= 0 && g.variant <= 8 && g.block >= 64 && g.block <= (g.variant >= 5 ? 512 : 256) &&
+         g.block % 64 == 0 && g.tz >= 1 && (g.nt == 0 || g.nt == 1) && (g.flip == 0 || g.flip == 1);
+}
+
+// "variant,block,tz,grid,nt,flip" with an optional ";variant,block,tz,grid,nt,flip" naming the
+// one-step tiling of a two-step one; n_min: fields the first part needs (the rest default to 0).
+bool parse_tuned(const char* v, int n_min, Tuned* out) {
+  Tuned t;
+  StepConfig& c = t.cfg;
+  c = StepConfig{0, 0, 0, 0, 0, 0, 0};
+  int used = 0;
+  const int n = sscanf(v, "%d,%d,%d,%d,%d,%d%n", &c.variant, &c.block, &c.tz, &c.grid, &c.nt, &c.flip, &used);
+  if (n < n_min) return false;
+  if (n < 6) {   // fewer fields: no companion, and nt/flip as given or 0
+    if (n < 5) c.nt = 0;
+    c.flip = 0;
+    used = 0;
+  }
+  if (!valid_cfg(c)) return false;
+  if (n == 6 && v[used] == ';') {
+    StepConfig& d = t.single;
+    d = StepConfig{0, 0, 0, 0, 0, 0, 0};
+    if (sscanf(v + used + 1, "%d,%d,%d,%d,%d,%d", &d.variant, &d.block, &d.tz, &d.grid, &d.nt, &d.flip) != 6 ||
+        !valid_cfg(d) || d.variant == 8)
+      return false;
+  }
+  if (c.variant == 8 && t.single.variant < 0) t.single = StepConfig{0, 256, 4, 0, 0, 0, 0};
+  *out = t;
+  return true;
+}
+
+std::string cfg_text(const StepConfig& g) {
+  return std::to_string(g.variant) + "," + std::to_string(g.block) + "," + std::to_string(g.tz) + "," +
+         std::to_string(g.grid) + "," + std::to_string(g.nt) + "," + std::to_string(g.flip);
+}
+
+// Tuning cache file (TL_TUNE_CACHE): a JSON object {"<workload key>": "variant,block,tz,grid,nt,flip", ...}
+// (a two-step tiling followed by ";" and its one-step companion).  The keys (architecture,
+// precision code, group width, launch mode, each group's dims and RHS) hold no quote or
+// backslash, so the file is read and written with plain string handling; a missing,
+// unreadable or malformed file is an empty cache.
 void tune_file_load(tl_ctx* c) {
   std::ifstream in(c->tune_file);
   if (!in) return;
@@ -237,12 +283,9 @@ void tune_file_load(tl_ctx* c) {
     const size_t v0 = k1 == std::string::npos ? k1 : t.find('"', k1 + 1);
     const size_t v1 = v0 == std::string::npos ? v0 : t.find('"', v0 + 1);
     if (v1 == std::string::npos) break;
-    StepConfig cfg{};
+    Tuned tu;
     const std::string val = t.substr(v0 + 1, v1 - v0 - 1);
-    if (sscanf(val.c_str(), "%d,%d,%d,%d,%d,%d", &cfg.variant, &cfg.block, &cfg.tz, &cfg.grid, &cfg.nt, &cfg.flip) == 6 &&
-        cfg.variant >= 0 && cfg.variant <= 7 && cfg.block >= 64 && cfg.block <= 512 && cfg.block % 64 == 0 &&
-        cfg.tz >= 1 && (cfg.nt == 0 || cfg.nt == 1) && (cfg.flip == 0 || cfg.flip == 1))
-      c->tune[t.substr(k0 + 1, k1 - k0 - 1)] = cfg;
+    if (parse_tuned(val.c_str(), 6, &tu)) c->tune[t.substr(k0 + 1, k1 - k0 - 1)] = tu;
     pos = v1 + 1;
   }
 }
@@ -256,9 +299,10 @@ void tune_file_save(const tl_ctx* c) {
     out << "{\n";
     size_t k = 0;
     for (const auto& kv : c->tune) {
-      const StepConfig& g = kv.second;
-      out << "  \"" << kv.first << "\": \"" << g.variant << "," << g.block << "," << g.tz << "," << g.grid << ","
-          << g.nt << "," << g.flip << "\"" << (++k < c->tune.size() ? ",\n" : "\n");
+      const Tuned& g = kv.second;
+      out << "  \"" << kv.first << "\": \"" << cfg_text(g.cfg)
+          << (g.cfg.variant == 8 ? ";" + cfg_text(g.single) : std::string()) << "\""
+          << (++k < c->tune.size() ? ",\n" : "\n");
     }
     out << "}\n";
     if (!out) return;
@@ -300,20 +344,26 @@ struct tl_plan {
   char* buf[2] = {nullptr, nullptr};
   int cur = 0;
 
-  // device tables: step groups, per-job pack offsets, reduction fields, partials
+  // device tables: the step groups of both tilings, per-job pack offsets, reduction fields, partials
   char* tables = nullptr;
-  StepGroup* groups_dev = nullptr;
   int64_t* packoff_dev = nullptr;
   std::vector<int64_t> packoff_first;   // index of job j's first entry in packoff_dev
   tl::RedField* red_dev = nullptr;
   double* partials = nullptr;
   int64_t max_v3 = 0;
 
-  std::vector<StepGroup> groups_host;
-  int n_tiles = 0;
-  int64_t lds = 0;                      // dynamic LDS bytes of the step launch (variant 5)
-  StepConfig cfg{0, 256, 4, 0, 0};
-  bool ready = false;                   // tuning done (or not requested) and table uploaded
+  // A step tiling and its work list (device table dev, host copy host).
+  struct Tiling {
+    StepConfig cfg{0, 256, 4, 0, 0, 0, 0};
+    StepGroup* dev = nullptr;
+    std::vector<StepGroup> host;
+    int n_tiles = 0;
+    int64_t lds = 0;                    // dynamic LDS bytes of its launches (variants 5-8)
+  };
+  Tiling tile;                          // the step tiling
+  Tiling single;                        // when tile runs two steps per launch: the one-step
+                                        // tiling of the last step of an odd count
+  bool ready = false;                   // tuning done (or not requested) and tables uploaded
 
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 
@@ -340,7 +390,13 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
     s.Lz = g.L[2];
     s.Vp = (int32_t)jc.Vp;
     s.nr = gr.nr;
-    if (cfg.variant >= 5) {   // full-row tiles
+    if (cfg.variant == 8) {   // two steps per launch: blocks of k rows of one y chain
+      const int D = tl::hop_of(p->prec);
+      s.rows = tl::fuse_rows(g.L[0], g.L[1], D, cfg.block);
+      if (s.rows == 0) return TL_ERR_UNSUPPORTED;
+      const int ychains = (D == 2 && !(g.L[1] & 1)) ? 2 : 1;
+      s.n_xy_tiles = ychains * (g.L[1] / ychains / s.rows);
+    } else if (cfg.variant >= 5) {   // full-row tiles
       s.rows = tl::lds_rows(g.L[0], g.L[1], cfg.block);
       if (s.rows == 0) return TL_ERR_UNSUPPORTED;
       s.n_xy_tiles = g.L[1] / s.rows;
@@ -364,60 +420,110 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
   return TL_OK;
 }
 
-// Dynamic LDS bytes of a configuration (variant 5), -1 if it does not fit.
+// Dynamic LDS bytes of a configuration (variants 5-8), -1 if it does not fit.
 int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<StepGroup>& gs) {
   if (cfg.variant < 5) return 0;
   int64_t mx = 0;
   const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
-  for (const auto& g : gs) mx = std::max(mx, tl::lds_bytes(p->prec, R, g.Lx, g.rows));
+  for (const auto& g : gs)
+    mx = std::max(mx, cfg.variant == 8 ? tl::lds_bytes_fuse2(p->prec, R, g.Lx, g.rows)
+                                       : tl::lds_bytes(p->prec, R, g.Lx, g.rows));
   return mx <= 160 * 1024 ? mx : -1;
 }
 
-int plan_upload_groups(tl_plan* p, const StepConfig& cfg) {
-  if (tl::is_one(p->prec) && cfg.variant != 0 && cfg.variant != 4 && cfg.variant != 7)
-    return fail(p->ctx, TL_ERR_UNSUPPORTED, "one-link smearing runs the step variants 0, 4 and 7 only");
-  if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1)
-    return fail(p->ctx, TL_ERR_UNSUPPORTED, "the LDS-staged step kernels take FP64 groups of one RHS only");
+// Whether cfg applies to this plan (its work list exists and fits in LDS); reason on failure.
+bool tiling_applies(const tl_plan* p, const StepConfig& cfg, const char** reason) {
+  if (tl::is_one(p->prec) && cfg.variant != 0 && cfg.variant != 4 && cfg.variant != 7 && cfg.variant != 8) {
+    *reason = "one-link smearing runs the step variants 0, 4, 7 and 8 only";
+    return false;
+  }
+  if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1) {
+    *reason = "the LDS-staged step kernels take FP64 groups of one RHS only";
+    return false;
+  }
+  if (cfg.variant == 8 && (p->flags & TL_PLAIN)) {
+    *reason = "TL_PLAIN runs one step per launch";
+    return false;
+  }
   std::vector<StepGroup> gs;
-  if (make_groups(p, cfg, &gs) != TL_OK)
-    return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list too long, or tiling not applicable to these lattices");
+  if (make_groups(p, cfg, &gs) != TL_OK) {
+    *reason = "work list too long, or tiling not applicable to these lattices";
+    return false;
+  }
   const int64_t lds = plan_lds(p, cfg, gs);
-  if (lds < 0 || (lds > 0 && !p->ctx->big_lds))
-    return fail(p->ctx, TL_ERR_UNSUPPORTED, "tiling needs more LDS than this device allows");
-  p->lds = lds;
-  TL_TRY(upload(p->ctx, p->groups_dev, gs.data(), gs.size() * sizeof(StepGroup)));
-  p->groups_host = gs;
-  p->n_tiles = gs.empty() ? 0 : gs.back().tile_begin + gs.back().n_xy_tiles * gs.back().n_z_tiles;
+  if (lds < 0 || (lds > 0 && !p->ctx->big_lds)) {
+    *reason = "tiling needs more LDS than this device allows";
+    return false;
+  }
+  return true;
+}
+
+// Build cfg's work list and upload it into tiling t's device table.
+int upload_tiling(tl_plan* p, const StepConfig& cfg, tl_plan::Tiling* t) {
+  const char* why = nullptr;
+  if (!tiling_applies(p, cfg, &why)) return fail(p->ctx, TL_ERR_UNSUPPORTED, "%s", why);
+  std::vector<StepGroup> gs;
+  (void)make_groups(p, cfg, &gs);
+  TL_TRY(upload(p->ctx, t->dev, gs.data(), gs.size() * sizeof(StepGroup)));
+  t->cfg = cfg;
+  t->cfg.rows64 = std::all_of(gs.begin(), gs.end(), [](const StepGroup& g) { return g.Lx == 64; }) ? 1 : 0;
+  t->lds = plan_lds(p, cfg, gs);
+  t->host = gs;
+  t->n_tiles = gs.empty() ? 0 : gs.back().tile_begin + gs.back().n_xy_tiles * gs.back().n_z_tiles;
   return TL_OK;
 }
 
-// One step over every group (batched) or over one group (plain mode, g >= 0).
-// k: index of the step in its sequence (odd steps run reversed when the tiling flips).
-int plan_step(tl_plan* p, hipStream_t s, int parity, int g, int k) {
+// The plan's tilings from a tuned pair.
+int upload_tuned(tl_plan* p, const Tuned& tu) {
+  TL_TRY(upload_tiling(p, tu.cfg, &p->tile));
+  if (tu.cfg.variant == 8) TL_TRY(upload_tiling(p, tu.single, &p->single));
+  return TL_OK;
+}
+
+// One launch of tiling t over every group (batched) or over one group (plain mode, g >= 0),
+// from buffer `in` to buffer `out`: one step, or two for variant 8.  k: index of the launch
+// in its sequence (odd launches run reversed when the tiling flips).
+int plan_launch(tl_plan* p, const tl_plan::Tiling& t, hipStream_t s, const char* in, char* out, int g, int k) {
   tl_ctx* c = p->ctx;
-  int base = 0, n = p->n_tiles;
+  int base = 0, n = t.n_tiles;
   if (g >= 0) {
-    base = p->groups_host[g].tile_begin;
-    n = p->groups_host[g].n_xy_tiles * p->groups_host[g].n_z_tiles;
+    base = t.host[g].tile_begin;
+    n = t.host[g].n_xy_tiles * t.host[g].n_z_tiles;
   }
-  StepConfig cfg = p->cfg;
+  StepConfig cfg = t.cfg;
   cfg.rev = (cfg.flip && (k & 1)) ? 1 : 0;
   return launch(c, "smearing step", [&] {
-    return tl::launch_step(p->prec, p->width, cfg, p->groups_dev, (int)p->groups_host.size(), base, n,
-                           p->buf[parity], p->buf[parity ^ 1], p->alpha, p->beta, p->lds, s);
+    return tl::launch_step(p->prec, p->width, cfg, t.dev, (int)t.host.size(), base, n, in, out, p->alpha, p->beta,
+                           t.lds, s);
   });
+}
+
+int plan_step(tl_plan* p, hipStream_t s, int parity, int g, int k) {
+  return plan_launch(p, p->tile, s, p->buf[parity], p->buf[parity ^ 1], g, k);
+}
+
+// Launches of one run of the n steps (each flips the resident buffer).
+int plan_launches(const tl_plan* p) {
+  return p->tile.cfg.variant == 8 ? p->n_steps / 2 + (p->n_steps & 1) : p->n_steps;
 }
 
 // Queue the n steps starting from buffer `parity` on stream s.
 int plan_enqueue(tl_plan* p, hipStream_t s, int parity) {
   if (p->flags & TL_PLAIN) {
-    for (int g = 0; g < (int)p->groups_host.size(); g++) {
+    for (int g = 0; g < (int)p->tile.host.size(); g++) {
       int q = parity;
       for (int k = 0; k < p->n_steps; k++) {
         TL_TRY(plan_step(p, s, q, g, k));
         q ^= 1;
       }
     }
+  } else if (p->tile.cfg.variant == 8) {
+    int q = parity;
+    for (int k = 0; k < p->n_steps / 2; k++) {
+      TL_TRY(plan_step(p, s, q, -1, k));
+      q ^= 1;
+    }
+    if (p->n_steps & 1) TL_TRY(plan_launch(p, p->single, s, p->buf[q], p->buf[q ^ 1], -1, 0));
   } else {
     int q = parity;
     for (int k = 0; k < p->n_steps; k++) {
@@ -441,18 +547,19 @@ std::string tune_key(const tl_plan* p) {
 
 // Time every candidate tiling on the plan's own data (buffer cur -> cur^1,
 // which leaves the input untouched), require each candidate's output to be
-// bit-identical to the first candidate's, keep the fastest.
+// bit-identical to the first candidate's, keep the fastest.  Then, for batched
+// plans of two or more steps, time the two-step tilings against two launches
+// of that winner (output bit-identical to them, time per step compared).
 int plan_autotune(tl_plan* p) {
   tl_ctx* c = p->ctx;
   const std::string key = tune_key(p);
   auto hit = c->tune.find(key);
   if (hit != c->tune.end()) {
-    p->cfg = hit->second;
     c->stats.tune_hits++;
-    return plan_upload_groups(p, p->cfg);
+    return upload_tuned(p, hit->second);
   }
   c->stats.tune_sweeps++;
-  std::vector<StepConfig> cands;
+  std::vector<StepConfig> cands, cands2;
   const int cu = std::max(c->n_cu, 1);
   for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
     const bool lds_variant = variant >= 5;
@@ -468,6 +575,12 @@ int plan_autotune(tl_plan* p) {
           for (int nt : {0, 1})
             for (int flip : {0, 1}) cands.push_back({variant, block, tz, grid, nt, flip, 0});
   }
+  if (!(p->flags & TL_PLAIN) && p->n_steps >= 2 && c->big_lds && !(tl::vprec(p->prec) == tl::F64 && p->width > 1))
+    for (int block : {512, 448, 384, 320, 256})
+      for (int tz : {4, 8, 16})
+        for (int grid : {0, cu})
+          for (int nt : {0, 1})
+            for (int flip : {0, 1}) cands2.push_back({8, block, tz, grid, nt, flip, 0});
   void* ref = nullptr;
   void* flag_mem = nullptr;
   TL_TRY(dev_alloc(c, &ref, p->buf_bytes));
@@ -479,34 +592,23 @@ int plan_autotune(tl_plan* p) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = fail(c, TL_ERR_HIP, "hipEventCreate failed");
-  float best = 1e30f;
-  StepConfig best_cfg = cands[0];
   const int reps = 10;
-  for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
-    p->cfg = cands[ci];
-    if (p->cfg.variant >= 5) {   // only where every lattice has a row tiling that fits in LDS
-      std::vector<StepGroup> gs;
-      if (make_groups(p, p->cfg, &gs) != TL_OK || plan_lds(p, p->cfg, gs) < 0) continue;
-    }
-    rc = plan_upload_groups(p, p->cfg);
-    if (rc != TL_OK) break;
-    const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
-    for (int w = 0; w < 2 && rc == TL_OK; w++) rc = plan_step(p, c->stream, p->cur, g_lim, w);
-    if (rc != TL_OK) break;
+  const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
+  // time reps launches of p->tile (after two untimed), then compare the output with ref
+  // (have_ref false: keep it as ref instead); ms: per launch
+  auto trial = [&](bool have_ref, float* ms, bool* same) -> int {
+    for (int w = 0; w < 2; w++) TL_TRY(plan_step(p, c->stream, p->cur, g_lim, w));
     (void)hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps && rc == TL_OK; k++) rc = plan_step(p, c->stream, p->cur, g_lim, k);
+    for (int k = 0; k < reps; k++) TL_TRY(plan_step(p, c->stream, p->cur, g_lim, k));
     (void)hipEventRecord(e1, c->stream);
-    if (rc != TL_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = fail(c, TL_ERR_HIP, "autotune timing failed");
-      break;
-    }
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    bool same = true;
-    if (ci == 0) {
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(c, TL_ERR_HIP, "autotune timing failed");
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t / reps;
+    *same = true;
+    if (!have_ref) {
       if (hipMemcpyAsync(ref, p->buf[p->cur ^ 1], p->buf_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        rc = fail(c, TL_ERR_HIP, "autotune reference copy failed");
+        return fail(c, TL_ERR_HIP, "autotune reference copy failed");
     } else {
       int one = 0;
       (void)hipMemsetAsync(flag_mem, 0, sizeof(int), c->stream);
@@ -514,15 +616,62 @@ int plan_autotune(tl_plan* p) {
                                static_cast<int*>(flag_mem), c->stream);
       (void)hipMemcpyAsync(&one, flag_mem, sizeof(int), hipMemcpyDeviceToHost, c->stream);
       (void)hipStreamSynchronize(c->stream);
-      same = one == 0;
+      *same = one == 0;
     }
+    return TL_OK;
+  };
+  auto log = [&](const StepConfig& g, float ms_step, bool same) {
     if (c->log)
       fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d flip=%d: %.4f ms/step%s\n",
-              key.c_str(), p->cfg.variant, p->cfg.block, p->cfg.tz, p->cfg.grid, p->cfg.nt, p->cfg.flip, ms / reps,
+              key.c_str(), g.variant, g.block, g.tz, g.grid, g.nt, g.flip, ms_step,
               same ? "" : "  OUTPUT DIFFERS - rejected");
+  };
+  float best = 1e30f;
+  StepConfig best_cfg = cands[0];
+  bool have_ref = false;
+  for (size_t ci = 0; ci < cands.size() && rc == TL_OK; ci++) {
+    const char* why = nullptr;
+    if (!tiling_applies(p, cands[ci], &why)) continue;
+    rc = upload_tiling(p, cands[ci], &p->tile);
+    if (rc != TL_OK) break;
+    float ms = 0.0f;
+    bool same = true;
+    rc = trial(have_ref, &ms, &same);
+    if (rc != TL_OK) break;
+    have_ref = true;
+    log(p->tile.cfg, ms, same);
     if (same && ms < best) {
       best = ms;
-      best_cfg = p->cfg;
+      best_cfg = p->tile.cfg;
+    }
+  }
+  Tuned tu;
+  tu.cfg = best_cfg;
+  if (rc == TL_OK && !cands2.empty()) {
+    // reference: two launches of the one-step winner, buffer cur -> cur^1 -> ref
+    rc = upload_tiling(p, best_cfg, &p->single);
+    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur], p->buf[p->cur ^ 1], g_lim, 0);
+    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur ^ 1], static_cast<char*>(ref), g_lim, 1);
+    float best2 = 1e30f;
+    StepConfig best2_cfg{};
+    for (size_t ci = 0; ci < cands2.size() && rc == TL_OK; ci++) {
+      const char* why = nullptr;
+      if (!tiling_applies(p, cands2[ci], &why)) continue;
+      rc = upload_tiling(p, cands2[ci], &p->tile);
+      if (rc != TL_OK) break;
+      float ms = 0.0f;
+      bool same = true;
+      rc = trial(true, &ms, &same);
+      if (rc != TL_OK) break;
+      log(p->tile.cfg, ms / 2, same);
+      if (same && ms / 2 < best2) {
+        best2 = ms / 2;
+        best2_cfg = p->tile.cfg;
+      }
+    }
+    if (rc == TL_OK && best2 < best) {
+      tu.cfg = best2_cfg;
+      tu.single = best_cfg;
     }
   }
   (void)hipStreamSynchronize(c->stream);
@@ -531,34 +680,24 @@ int plan_autotune(tl_plan* p) {
   (void)hipFree(ref);
   (void)hipFree(flag_mem);
   if (rc != TL_OK) return rc;
-  p->cfg = best_cfg;
-  c->tune[key] = best_cfg;
+  c->tune[key] = tu;
   if (!c->tune_file.empty()) tune_file_save(c);
-  return plan_upload_groups(p, p->cfg);
+  return upload_tuned(p, tu);
 }
 
-// TL_TILE="variant,block,tz,grid[,nt]" fixes the step configuration of every plan
-// (no tuning): used to profile or sweep one tiling at a time.
-bool tile_override(StepConfig* cfg) {
+// TL_TILE="variant,block,tz,grid[,nt[,flip]]" fixes the step tiling of every plan (no tuning):
+// used to profile or sweep one tiling at a time.  A two-step tiling (variant 8) may name its
+// one-step companion after a ";" (default: variant 0, 256 threads, tz 4).
+bool tile_override(Tuned* tu) {
   const char* e = getenv("TL_TILE");
-  if (!e) return false;
-  StepConfig c{};
-  const int n = sscanf(e, "%d,%d,%d,%d,%d,%d", &c.variant, &c.block, &c.tz, &c.grid, &c.nt, &c.flip);
-  if (n < 4) return false;
-  if (n < 5) c.nt = 0;
-  if (n < 6) c.flip = 0;
-  if ((c.nt != 0 && c.nt != 1) || (c.flip != 0 && c.flip != 1)) return false;
-  if (c.variant < 0 || c.variant > 7 || c.block < 64 || c.block > (c.variant >= 5 ? 512 : 256) || c.block % 64 || c.tz < 1) return false;
-  *cfg = c;
-  return true;
+  return e && parse_tuned(e, 4, tu);
 }
 
 int plan_prepare(tl_plan* p) {
   if (p->ready) return TL_OK;
-  StepConfig forced{};
+  Tuned forced;
   if (tile_override(&forced)) {
-    p->cfg = forced;
-    TL_TRY(plan_upload_groups(p, p->cfg));
+    TL_TRY(upload_tuned(p, forced));
   } else if ((p->flags & TL_AUTOTUNE) && p->n_steps > 0) {
     TL_TRY(plan_autotune(p));
   }
@@ -963,7 +1102,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
       p->buf[k] = static_cast<char*>(b);
     }
     const size_t n_res = p->res.size();
-    const size_t gbytes = align256(p->groups.size() * sizeof(StepGroup));
+    const size_t gbytes = 2 * align256(p->groups.size() * sizeof(StepGroup));   // two tilings
     const size_t obytes = align256(n_res * sizeof(int64_t));
     const size_t rbytes = align256(n_res * sizeof(tl::RedField));
     const size_t pbytes = align256((size_t)tl::red_partials_doubles((int)n_res, p->max_v3) * sizeof(double));
@@ -973,7 +1112,8 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
       p->tables = static_cast<char*>(t);
     }
     if (rc == TL_OK) {
-      p->groups_dev = reinterpret_cast<StepGroup*>(p->tables);
+      p->tile.dev = reinterpret_cast<StepGroup*>(p->tables);
+      p->single.dev = reinterpret_cast<StepGroup*>(p->tables + gbytes / 2);
       p->packoff_dev = reinterpret_cast<int64_t*>(p->tables + gbytes);
       p->red_dev = reinterpret_cast<tl::RedField*>(p->tables + gbytes + obytes);
       p->partials = reinterpret_cast<double*>(p->tables + gbytes + obytes + rbytes);
@@ -1002,7 +1142,7 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
         if (hipMemsetAsync(p->buf[k], 0, p->buf_bytes, c->stream) != hipSuccess)
           rc = fail(c, TL_ERR_HIP, "hipMemsetAsync failed");
     }
-    if (rc == TL_OK) rc = plan_upload_groups(p, p->cfg);
+    if (rc == TL_OK) rc = upload_tiling(p, p->tile.cfg, &p->tile);
     if (rc != TL_OK) return rc;
     // info
     tl_plan_info& in = p->info;
@@ -1059,7 +1199,7 @@ int tl_plan_run(tl_plan* p) {
     } else {
       TL_TRY(plan_enqueue(p, c->stream, p->cur));
     }
-    p->cur ^= (p->n_steps & 1);
+    p->cur ^= (plan_launches(p) & 1);
     return TL_OK;
   } catch (...) {
     return host_failure(p ? p->ctx : nullptr);
@@ -1177,13 +1317,15 @@ int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
   try {
     if (!p || !info) return TL_ERR_ARG;
     *info = p->info;
-    info->n_tiles = p->n_tiles;
-    info->variant = p->cfg.variant;
-    info->block = p->cfg.block;
-    info->tz = p->cfg.tz;
-    info->grid = p->cfg.grid > 0 ? std::min(p->cfg.grid, p->n_tiles) : p->n_tiles;
-    info->nt = p->cfg.nt;
-    info->flip = p->cfg.flip;
+    const tl_plan::Tiling& t = p->tile;
+    info->n_tiles = t.n_tiles;
+    info->variant = t.cfg.variant;
+    info->block = t.cfg.block;
+    info->tz = t.cfg.tz;
+    info->grid = t.cfg.grid > 0 ? std::min(t.cfg.grid, t.n_tiles) : t.n_tiles;
+    info->nt = t.cfg.nt;
+    info->flip = t.cfg.flip;
+    info->steps_per_launch = t.cfg.variant == 8 ? 2 : 1;
     return TL_OK;
   } catch (...) {
     return host_failure(p ? p->ctx : nullptr);
@@ -1199,6 +1341,8 @@ int tl_plan_destroy(tl_plan* p) {
     return host_failure(nullptr);
   }
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1227,6 +1371,8 @@ std::string smear_signature(const tl_job* jobs, int n_jobs, int n_steps, double 
 }
 
 }  // namespace
+
+extern "C" {
 
 int tl_smear(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, double sigma, int prec, unsigned flags) {
   try {

@@ -1019,6 +1019,11 @@ __global__ __launch_bounds__(512) void step_zchain(const StepGroup* __restrict__
 // packed words are widened by finish_w).
 constexpr int raw_words(int P) { return is_w12(P) ? 12 : ((P & 3) == BF16 ? 9 : 18); }
 
+// Forms whose LDS-staged kernels take the backward x two-link from a neighbouring lane on
+// rows of 64 sites: FP32 and eighteen-real F16S (the others would spill the registers the
+// second code path needs).
+constexpr bool lane_xbw(int P) { return (P & 3) == F32 || (P & 7) == F16S; }
+
 // The value v of lane src of the wave (src in bytes: lane * 4).
 __device__ __forceinline__ float lane_get(float v, int src) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
@@ -1077,10 +1082,7 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
     const bool active = trow < rows;
     // rows of 64 sites: a wave is one row and lane x holds W_x at x, so the backward x
     // two-link W_x(x - D) is lane x - D's forward one, taken across lanes instead of loaded
-    // (FP32 forms and eighteen-real F16S; the other forms would spill the registers the
-    // second code path needs)
-    constexpr bool kXlane = (P & 3) == F32 || (P & 7) == F16S;
-    const bool xlane = kXlane && Lx == 64;
+    const bool xlane = lane_xbw(P) && Lx == 64;
     const int row = active ? trow : 0;
     const int y = y0 + row;
     const int xy = y * Lx + x;
@@ -1280,7 +1282,386 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
   }
 }
 
+// Variant 8: two smearing steps per launch (temporal blocking).  The second
+// step's input, the first step's output, never leaves the workgroup: each
+// step-one result is rounded to the storage format in registers, exactly as a
+// store and a reload would round it, and kept in LDS, so the pair of steps
+// reads the two-links and the input once from memory and writes only the
+// second step's output.  The arithmetic of both steps is that of the one-step
+// kernels, so the result is bit-identical to two launches of any of them.
+//
+// Hops of D = 2 sites decouple the lattice into chains: the rows y, y+2, ...
+// (two chains for even Ly, one for odd) and the planes z, z+2, ... (likewise).
+// A tile is k consecutive rows of one y chain (full x extent) and a chunk of
+// consecutive positions of one z chain.  The first step runs on the tile's
+// rows plus one chain row on each side, which the second step's y hops read;
+// its input plane is staged in LDS with a further chain row on each side.
+// The march along the z chain keeps, per thread, its own column: stage s
+// computes step one at march position m = s - 1 (input planes m - 1, m, m + 1)
+// and step two at position m - 1 (step-one planes m - 2, m - 1, m), so a chunk
+// of nz positions runs nz + 2 stages.  The own slots of two LDS buffers hold
+// the input planes m and m - 1, two more the step-one planes m and m - 1; the
+// z two-links of the three links m - 2 .. m + 1 stay in registers.  One
+// barrier per stage.  With one-link fields (D = 1) the chains are all rows and
+// all planes.  XL: every group's rows are 64 sites long (a wave is one row, and the
+// backward x two-link comes from the lane D to the left), fixed at compile time so
+// that no register is set aside for loading it.
+template <int P, int R, bool NT, bool XL>
+__global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ groups, int n_groups,
+                                                  int tile_base, int n_tiles, int tz, int rev,
+                                                  const char* __restrict__ in, char* __restrict__ out,
+                                                  typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
+  using PL = Planes<P>;
+  using real = typename Fmt<P>::real;
+  using c2 = typename Complex2<real>::type;
+  constexpr int D = hop_of(P);
+  constexpr bool xlane = XL && lane_xbw(P);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  c2* const lds = reinterpret_cast<c2*>(lds_raw);
+  const TileSweep sw = xcd_sweep(n_tiles, rev);
+  for (int mt = 0; mt < sw.n; mt++) {
+    const int tile = tile_base + sw.tile(mt);
+    const StepGroup& g = groups[find_group(groups, n_groups, tile)];
+    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, k = g.rows;
+    const int64_t Vp = g.Vp;
+    const int local = tile - g.tile_begin;
+    const int tzi = local / g.n_xy_tiles;          // z chain chunk index: n_z_tiles = chains * chunks
+    const int yt = local - tzi * g.n_xy_tiles;     // y chain block index: n_xy_tiles = chains * blocks
+    const int ychains = (D == 2 && !(Ly & 1)) ? 2 : 1;
+    const int ylen = Ly / ychains;
+    const int yblocks = ylen / k;
+    const int ych = yt / yblocks, yb = yt - ych * yblocks;
+    const int zchains = (D == 2 && !(Lz & 1)) ? 2 : 1;
+    const int zlen = Lz / zchains;
+    const int chunks = (zlen + tz - 1) / tz;
+    const int zch = tzi / chunks, chunk = tzi - zch * chunks;
+    const int LxLy = Lx * Ly;
+    const int t = (int)threadIdx.x;
+    const int trow = t / Lx, x = t - trow * Lx;
+    // thread rows 0 .. k+1 are the chain rows -1 .. k of the block: step one on all of them,
+    // step two on rows 1 .. k
+    const bool inreg = trow < k + 2;
+    const int row = inreg ? trow : 0;
+    const bool core = inreg && row >= 1 && row <= k;
+    auto lat_row = [&](int rel) { return wrap_sel(ych + D * wrap_sel(yb * k + rel, ylen), Ly); };
+    const int y = lat_row(row - 1);
+    const int xy = y * Lx + x;
+    const int xbw = y * Lx + wrap_sel(x - D, Lx);
+    const int ybw = lat_row(row - 2) * Lx + x;
+    // LDS: input planes (k + 4 rows: chain rows -2 .. k+1), step-one planes (k + 2 rows)
+    const int nA = (k + 4) * Lx, nB = (k + 2) * Lx;
+    c2* const A0 = lds;
+    c2* const A1 = A0 + R * 3 * nA;
+    c2* const B0 = A1 + R * 3 * nA;
+    c2* const B1 = B0 + R * 3 * nB;
+    const int xf = wrap_sel(x + D, Lx), xb = wrap_sel(x - D, Lx);
+    const int oA = (row + 1) * Lx + x, aXf = (row + 1) * Lx + xf, aXb = (row + 1) * Lx + xb;
+    const int aYf = (row + 2) * Lx + x, aYb = row * Lx + x;
+    const int oB = row * Lx + x, bXf = row * Lx + xf, bXb = row * Lx + xb;
+    const int bYf = (row + 1) * Lx + x, bYb = (row - 1) * Lx + x;   // read by core rows only
+    // the input plane's outer rows (chain rows -2 and k+1) are loaded by the threads of rows
+    // 0 and k+1, which have no step-two site, while the others run step two
+    const bool edge = inreg && !core;
+    const int hxy = lat_row(row == 0 ? -2 : k + 1) * Lx + x;
+    const int hslot = (row == 0 ? 0 : k + 3) * Lx + x;
+    const char* wp[3][PL::NW];
+#pragma unroll
+    for (int mu = 0; mu < 3; mu++) PL::w(g.W + mu * g.w_mu_stride, Vp, wp[mu]);
+    const int nr = g.nr;
+    const char* ip[R][PL::NV];
+    char* op[R][PL::NV];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t o = g.psi_off + (int64_t)min(r, nr - 1) * g.rhs_stride;
+      PL::v(in + o, Vp, ip[r]);
+      PL::v(out + o, Vp, op[r]);
+    }
+    const int k0 = chunk * tz;
+    const int nz = min(k0 + tz, zlen) - k0;        // step-two positions of this chunk
+    const bool up = ((chunk & 1) == 0) != (rev != 0);
+    const int kf = up ? k0 : k0 + nz - 1;
+    const int step = up ? D : -D;
+    const int zf = wrap_step(zch + D * kf, 0, Lz);   // march position 0
+    int zc = wrap_step(zf, -step, Lz);                // march position -1: step one's first plane
+    const int zbb = wrap_step(zf, -2 * step, Lz);     // march position -2
+    // z link between march positions a and a + 1: W_z at the lower of their planes
+    auto link_site = [&](int za, int za1) { return (uint32_t)((up ? za : za1) * LxLy + xy); };
+    real ahd[R][6];          // input colour vectors at march position m + 1 (own column)
+    real lk[2][18];          // z links (m-1, m) and (m, m+1); step two reloads (m-2, m-1)
+    real mxf[18], mxb[18], myf[18], myb[18];
+    // a workgroup with several tiles: every thread has finished reading the previous
+    // tile's LDS before its own slots are written
+    __syncthreads();
+    {
+      real bh[R][6], cu[R][6], hv[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        PL::load_v(ip[r], (uint32_t)(zbb * LxLy + xy), bh[r]);
+        PL::load_v(ip[r], (uint32_t)(zc * LxLy + xy), cu[r]);
+        PL::load_v(ip[r], (uint32_t)(zf * LxLy + xy), ahd[r]);
+        PL::load_v(ip[r], (uint32_t)(zc * LxLy + hxy), hv[r]);
+      }
+      PL::load_w(wp[2], link_site(zbb, zc), lk[0]);
+      PL::load_w(wp[2], link_site(zc, zf), lk[1]);
+      const uint32_t zo = (uint32_t)(zc * LxLy);
+      PL::load_w_raw(wp[0], zo + (uint32_t)xy, mxf);
+      if (!xlane) PL::load_w_raw(wp[0], zo + (uint32_t)xbw, mxb);
+      PL::load_w_raw(wp[1], zo + (uint32_t)xy, myf);
+      PL::load_w_raw(wp[1], zo + (uint32_t)ybw, myb);
+      if (inreg) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            A0[(r * 3 + c) * nA + oA] = c2{cu[r][2 * c], cu[r][2 * c + 1]};
+            A1[(r * 3 + c) * nA + oA] = c2{bh[r][2 * c], bh[r][2 * c + 1]};
+          }
+      }
+      if (edge) {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) A0[(r * 3 + c) * nA + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
+      }
+    }
+    int s = 0;
+    // one stage; S2: step two runs (s >= 2); MORE: a further stage follows
+    auto stage = [&](auto s2_c, auto more_c) {
+      constexpr bool S2 = decltype(s2_c)::value;
+      constexpr bool MORE = decltype(more_c)::value;
+      const int zn = wrap_sel(zc + step, Lz);   // march position m + 1
+      const int zb = wrap_sel(zc - step, Lz);   // march position m - 1
+      c2* const Ac = (s & 1) ? A1 : A0;          // input plane m; own slots of Ao: plane m - 1
+      c2* const Ao = (s & 1) ? A0 : A1;          // (then plane m + 1, with its outer rows)
+      c2* const Bc = (s & 1) ? B1 : B0;          // own slots: step one at m - 2, then at m
+      c2* const Bo = (s & 1) ? B0 : B1;          // step one at m - 1
+      __syncthreads();
+      // ---- step one at plane zc, chain rows -1 .. k
+      if (xlane) {
+        const int src = ((x - D) & 63) * 4;
+#pragma unroll
+        for (int c = 0; c < raw_words(P); c++) mxb[c] = lane_get(mxf[c], src);
+      }
+      PL::finish_w(mxf);
+      PL::finish_w(mxb);
+      PL::finish_w(myf);
+      PL::finish_w(myb);
+      real acc[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+        real v[6];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aXf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(mxf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aXb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(mxb, v, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        real v[6];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aYf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mv_acc(myf, v, acc[r]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aYb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        mdv_acc(myb, v, acc[r]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // in-plane two-links of the next use (step two at plane zb, else step one at plane zn):
+      // x now, y after the z hops
+      const uint32_t zon = (uint32_t)((S2 ? zb : zn) * LxLy);
+      if constexpr (S2 || MORE) {
+        PL::load_w_raw(wp[0], zon + (uint32_t)xy, mxf);
+        if (!xlane) PL::load_w_raw(wp[0], zon + (uint32_t)xbw, mxb);
+      }
+      {
+        real bh[R][6];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) { const c2 w = Ao[(r * 3 + c) * nA + oA]; bh[r][2 * c] = w.x; bh[r][2 * c + 1] = w.y; }
+        if (up) {
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            mv_acc(lk[1], ahd[r], acc[r]);
+            mdv_acc(lk[0], bh[r], acc[r]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            mv_acc(lk[0], bh[r], acc[r]);
+            mdv_acc(lk[1], ahd[r], acc[r]);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (S2 || MORE) {
+        PL::load_w_raw(wp[1], zon + (uint32_t)xy, myf);
+        PL::load_w_raw(wp[1], zon + (uint32_t)ybw, myb);
+      }
+      real s1[R][6];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const c2 w = Ac[(r * 3 + c) * nA + oA];
+          s1[r][2 * c] = fma_(beta, acc[r][2 * c], alpha * w.x);
+          s1[r][2 * c + 1] = fma_(beta, acc[r][2 * c + 1], alpha * w.y);
+        }
+        PL::round_v(s1[r]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {   // input plane m + 1 becomes the next stage's current plane
+        if (inreg) {
+#pragma unroll
+          for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) Ao[(r * 3 + c) * nA + oA] = c2{ahd[r][2 * c], ahd[r][2 * c + 1]};
+        }
+      }
+      // ---- step two at plane zb, chain rows 0 .. k-1; meanwhile the edge rows load the outer
+      // rows of input plane m + 1 into Ao (whose outer rows were last read before this
+      // stage's barrier)
+      if constexpr (MORE) {
+        if (edge) {
+          real hv[R][6];
+#pragma unroll
+          for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(zn * LxLy + hxy), hv[r]);
+#pragma unroll
+          for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) Ao[(r * 3 + c) * nA + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
+        }
+      }
+      if constexpr (S2) {
+        real l0[18];   // z link (m-2, m-1)
+        if (core) PL::load_w(wp[2], link_site(wrap_sel(zb - step, Lz), zb), l0);
+        if (core) {
+          if (xlane) {
+            const int src = ((x - D) & 63) * 4;
+#pragma unroll
+            for (int c = 0; c < raw_words(P); c++) mxb[c] = lane_get(mxf[c], src);
+          }
+          PL::finish_w(mxf);
+          PL::finish_w(mxb);
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
+            real v[6];
+#pragma unroll
+            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            mv_acc(mxf, v, acc[r]);
+#pragma unroll
+            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            mdv_acc(mxb, v, acc[r]);
+          }
+        }
+        // the next stage's step one at plane zn: x two-links as soon as these x hops are done,
+        // y two-links after the y hops
+        const uint32_t zno = (uint32_t)(zn * LxLy);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (MORE) {
+          PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
+          if (!xlane) PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+        }
+        if (core) {
+          PL::finish_w(myf);
+          PL::finish_w(myb);
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            real v[6];
+#pragma unroll
+            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bYf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            mv_acc(myf, v, acc[r]);
+#pragma unroll
+            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bYb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            mdv_acc(myb, v, acc[r]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (MORE) {
+          PL::load_w_raw(wp[1], zno + (uint32_t)xy, myf);
+          PL::load_w_raw(wp[1], zno + (uint32_t)ybw, myb);
+        }
+        if (core) {
+          real bh[R][6];
+#pragma unroll
+          for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) { const c2 w = Bc[(r * 3 + c) * nB + oB]; bh[r][2 * c] = w.x; bh[r][2 * c + 1] = w.y; }
+          if (up) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+              mv_acc(lk[0], s1[r], acc[r]);
+              mdv_acc(l0, bh[r], acc[r]);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+              mv_acc(l0, bh[r], acc[r]);
+              mdv_acc(lk[0], s1[r], acc[r]);
+            }
+          }
+          const uint32_t site = (uint32_t)(zb * LxLy + xy);
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            real o[6];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+              const c2 w = Bo[(r * 3 + c) * nB + oB];
+              o[2 * c] = fma_(beta, acc[r][2 * c], alpha * w.x);
+              o[2 * c + 1] = fma_(beta, acc[r][2 * c + 1], alpha * w.y);
+            }
+            if (r < nr) PL::template store_v<real, NT>(op[r], site, o);
+          }
+        }
+      }
+      if (inreg) {   // step one at m: the own slots of Bc (step one at m - 2 is no longer read)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+          for (int c = 0; c < 3; c++) Bc[(r * 3 + c) * nB + oB] = c2{s1[r][2 * c], s1[r][2 * c + 1]};
+      }
+#pragma unroll
+      for (int c = 0; c < 18; c++) lk[0][c] = lk[1][c];
+      if constexpr (MORE) {   // the next stage's input plane ahead and its z link
+        const int znn = wrap_sel(zn + step, Lz);
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(znn * LxLy + xy), ahd[r]);
+        PL::load_w(wp[2], link_site(zn, znn), lk[1]);
+      }
+      zc = zn;
+      s++;
+    };
+    stage(std::false_type{}, std::true_type{});   // step one at march position -1
+    stage(std::false_type{}, std::true_type{});   // step one at 0
+    for (int i = 1; i < nz; i++) stage(std::true_type{}, std::true_type{});
+    stage(std::true_type{}, std::false_type{});   // step one at nz, step two at nz - 1
+  }
+}
+
 constexpr int kMaxLds = 160 * 1024;   // LDS per compute unit on gfx950
+
+// Variant 8, with rows of 64 sites fixed at compile time where the form uses the lane exchange.
+template <int P, int R, bool NT>
+hipError_t launch_fuse2(const StepConfig& cfg, int grid, const StepGroup* groups, int n_groups, int tile_base,
+                        int n_tiles, const char* in, char* out, typename Fmt<P>::real a, typename Fmt<P>::real b,
+                        int64_t lds, hipStream_t s) {
+  if constexpr (lane_xbw(P)) {
+    if (cfg.rows64) {
+      step_fuse2<P, R, NT, true><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz,
+                                                                       cfg.rev, in, out, a, b);
+      return hipGetLastError();
+    }
+  }
+  step_fuse2<P, R, NT, false><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev,
+                                                                    in, out, a, b);
+  return hipGetLastError();
+}
 
 template <int P, int R, bool NT>
 hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_groups, int tile_base,
@@ -1293,17 +1674,20 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
   // (variant 5 has full-row tiles and its own block sizes: it never falls back, and the host
   // never selects it for FP64 groups wider than one RHS)
   if (cfg.variant >= 5 && vprec(P) == F64 && R > 1) return hipErrorInvalidValue;
-  if constexpr (is_one(P)) {   // one-link fields: hops of one site, variants 0, 4 and 7
+  if constexpr (is_one(P)) {   // one-link fields: hops of one site, variants 0, 4, 7 and 8
     const real a = (real)alpha, b = (real)beta;
     if (cfg.variant == 0)
       step_direct<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
     else if (cfg.variant == 4)
       step_rolled<P, R, NT><<<grid, cfg.block, 0, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out, a, b);
-    else if (cfg.variant == 7) {
+    else if (cfg.variant == 7 || cfg.variant == 8) {
       constexpr int R2 = (vprec(P) == F64) ? 1 : R;
       if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
-      step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev,
-                                                                in, out, a, b);
+      if (cfg.variant == 7)
+        step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev,
+                                                                  in, out, a, b);
+      else
+        return launch_fuse2<P, R2, NT>(cfg, grid, groups, n_groups, tile_base, n_tiles, in, out, a, b, lds, s);
     } else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1328,6 +1712,9 @@ hipError_t launch_step_n(const StepConfig& cfg, const StepGroup* groups, int n_g
       if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
       step_zpipe<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
                                                                 a, b);
+    } else if (cfg.variant == 8) {
+      if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
+      return launch_fuse2<P, R2, NT>(cfg, grid, groups, n_groups, tile_base, n_tiles, in, out, a, b, lds, s);
     } else if (cfg.variant == 6) {
       if (lds <= 0 || lds > kMaxLds) return hipErrorInvalidValue;
       step_zchain<P, R2, NT><<<grid, cfg.block, (size_t)lds, s>>>(groups, n_groups, tile_base, n_tiles, cfg.tz, cfg.rev, in, out,
@@ -1355,7 +1742,11 @@ template <int P, int R>
 hipError_t allow_lds() {
   if constexpr (is_one(P)) {
     for (const void* f : {reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
-                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
+                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, false, false>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, true, false>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, false, lane_xbw(P)>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, true, lane_xbw(P)>)}) {
       const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
       if (e != hipSuccess) return e;
     }
@@ -1366,7 +1757,11 @@ hipError_t allow_lds() {
                           reinterpret_cast<const void*>(&step_zchain<P, R, false>),
                           reinterpret_cast<const void*>(&step_zchain<P, R, true>),
                           reinterpret_cast<const void*>(&step_zpipe<P, R, false>),
-                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>)}) {
+                          reinterpret_cast<const void*>(&step_zpipe<P, R, true>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, false, false>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, true, false>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, false, lane_xbw(P)>),
+                          reinterpret_cast<const void*>(&step_fuse2<P, R, true, lane_xbw(P)>)}) {
       const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
       if (e != hipSuccess) return e;
     }
