@@ -297,6 +297,10 @@ def compact_lattice(lat):
     return L, U, [slices.index(t) for t in lat.t_of_rhs]
 
 
+KERNEL_NAMES = ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
+                "step_zpipe", "step_fuse2"]
+
+
 def measure_workload(ctx, torch, tl, dev, index, prec, plain=False, passes=5):
     """Step and pass rates, roofline fraction and oracle error of one of the other workloads."""
     from oracle import checks, core
@@ -343,10 +347,10 @@ def measure_workload(ctx, torch, tl, dev, index, prec, plain=False, passes=5):
     pass_ms = e0.elapsed_time(e1) / passes
     step_ms = plan.time(reps=5)
     info = plan.info()
-    # a launch moves bytes_per_step (W once, the input and the output once) for its one or two steps
+    # algorithmic bytes: those of every RHS-site-update (W, the input and the output once each)
     spl = info["steps_per_launch"]
     launch_ms = step_ms * wl.n_steps / ((wl.n_steps + spl - 1) // spl)
-    gbs = info["bytes_per_step"] / (launch_ms * 1e-3) / 1e9
+    gbs = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
     rec = {"workload": wl.name, "storage": prec, "rhs": sum(len(ts) for _, _, ts in lats),
            "step_us": round(step_ms * 1e3, 2), "launch_us": round(launch_ms * 1e3, 2), "steps_per_launch": spl,
            "pass_ms": round(pass_ms, 4),
@@ -528,25 +532,45 @@ def main():
     # replayed from the graph, gaps between them included); back-to-back replays outside the
     # timed region are reported beside it.
     info = plan.info()
-    spl = info["steps_per_launch"]   # 2: each launch runs two steps (W and the input read once)
+    # one launch runs spl steps (2: the two-step kernel, which reads W and its input once and
+    # writes only the second step's output); the algorithmic bytes are those of the RHS-site-
+    # updates it performs, 120 B each at FP32 and three RHS per W load (W, the input and the
+    # output once per update), so a two-step launch counts two steps' bytes against its time
+    spl = info["steps_per_launch"]
     launches = max(1, info["launches_per_step"] * ((wl.n_steps + spl - 1) // spl))
     step_ms = sum(a.elapsed_time(b) for a, b in run_events) / len(run_events) / launches
     isolated_ms = plan.time(reps=3) * wl.n_steps / launches
-    achieved = info["bytes_per_step"] / (step_ms * 1e-3) / 1e9
+    algo_bytes = info["bytes_per_step"] * spl
+    achieved = algo_bytes / (step_ms * 1e-3) / 1e9
     key = workload_key(args)
     tile = ",".join(str(info[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))
     traffic = measured_traffic(key, tile)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
-                           "step_zpipe", "step_fuse2"][info["variant"]],
-                "steps_per_launch": spl,
-                "algorithmic_bytes_per_launch": info["bytes_per_step"],
+                "kernel": KERNEL_NAMES[info["variant"]], "steps_per_launch": spl,
+                "algorithmic_bytes_per_launch": algo_bytes,
+                # what one launch must move at the least (W once, its input and its output once),
+                # and the share of HBM bandwidth the launch's counted traffic uses
+                "launch_min_bytes": info["bytes_per_step"],
+                "traffic_GBs": round(traffic / (step_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
                 "copy_GBs": round(copy_gbs, 1), "ceiling_GBs": ceiling["ceiling_GBs"],
                 "frac_of_ceiling": round(achieved / ceiling["ceiling_GBs"], 4),
                 "ceiling": {k: ceiling[k] for k in ("ceiling_kinds", "step_kinds_GBs", "bytes", "mix", "configs")}}
-    log(f"[bench] step kernel {step_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic")
+    log(f"[bench] step kernel ({spl} step(s) per launch) {step_ms * 1e3:.1f} us per launch, "
+        f"{achieved:.0f} GB/s algorithmic")
+    if spl == 2 and not args.no_extra:
+        # the fastest one-step tiling on the same resident data, for comparison
+        p1 = ctx.plan(jobs, wl.n_steps, wl.sigma, prec, args.flags | tl.TL_ONE_STEP)
+        p1.load()
+        ms1 = p1.time(reps=3)
+        i1 = p1.info()
+        a1 = i1["bytes_per_step"] / (ms1 * 1e-3) / 1e9
+        roofline["one_step"] = {"kernel": KERNEL_NAMES[i1["variant"]], "launch_ms": round(ms1, 5),
+                                "achieved": round(a1, 1), "frac": round(a1 / HBM_PEAK_GBS, 4),
+                                "tile": ",".join(str(i1[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))}
+        p1.close()
+        log(f"[bench] fastest one-step tiling: {roofline['one_step']}")
 
     # the pieces of a pass, timed alone on the same stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

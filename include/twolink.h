@@ -94,7 +94,8 @@ enum { TL_ONELINK = 32 };  /* OR into a precision: a one-link field and the one-
 enum {
     TL_PLAIN = 1u,      /* one right-hand side per launch, RHS in succession, eager launches */
     TL_GRAPH = 2u,      /* capture the n step launches in one HIP graph, replayed per run */
-    TL_AUTOTUNE = 4u    /* time the candidate tilings once and keep the fastest (cached per context) */
+    TL_AUTOTUNE = 4u,   /* time the candidate tilings once and keep the fastest (cached per context) */
+    TL_ONE_STEP = 8u    /* tune over tilings of one step per launch only (no two-step launches) */
 };
 
 /* reduction kinds.  TL_NORM2 and TL_DOT are the spatial sums over the sites x of one

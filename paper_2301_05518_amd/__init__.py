@@ -28,9 +28,9 @@ from dataclasses import dataclass
 from typing import Sequence
 
 from . import _lib
-from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_ONELINK, TL_PLAIN, TL_W12, TwolinkError  # noqa: F401
+from ._lib import PREC, TL_AUTOTUNE, TL_GRAPH, TL_ONE_STEP, TL_ONELINK, TL_PLAIN, TL_W12, TwolinkError  # noqa: F401
 
-__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE", "TL_W12", "TL_ONELINK",
+__all__ = ["Context", "Job", "Plan", "TwolinkError", "PREC", "TL_PLAIN", "TL_GRAPH", "TL_AUTOTUNE", "TL_ONE_STEP", "TL_W12", "TL_ONELINK",
            "twolinks_bytes", "library"]
 
 

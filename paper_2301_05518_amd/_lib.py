@@ -17,7 +17,7 @@ _BASE = {"f64": 0, "f32": 1, "f16s": 2, "bf16": 3}
 # "<prec>[-w12][-onelink]"
 PREC = {b + w + o: v | (TL_W12 if w else 0) | (TL_ONELINK if o else 0)
         for b, v in _BASE.items() for w in ("", "-w12") for o in ("", "-onelink")}
-TL_PLAIN, TL_GRAPH, TL_AUTOTUNE = 1, 2, 4
+TL_PLAIN, TL_GRAPH, TL_AUTOTUNE, TL_ONE_STEP = 1, 2, 4, 8
 TL_NORM2, TL_DOT, TL_SITE_NORM = 0, 1, 2
 
 # every symbol the header declares

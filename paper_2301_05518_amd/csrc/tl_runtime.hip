@@ -536,7 +536,7 @@ int plan_enqueue(tl_plan* p, hipStream_t s, int parity) {
 
 std::string tune_key(const tl_plan* p) {
   std::string k = p->ctx->arch + "|p" + std::to_string(p->prec) + "|w" + std::to_string(p->width) +
-                  ((p->flags & TL_PLAIN) ? "|plain" : "|batch");
+                  ((p->flags & TL_PLAIN) ? "|plain" : "|batch") + ((p->flags & TL_ONE_STEP) ? "|one" : "");
   for (const auto& g : p->groups) {
     const tl_geom& ge = p->jobs[g.job].job.g;
     k += "|" + std::to_string(ge.L[0]) + "x" + std::to_string(ge.L[1]) + "x" + std::to_string(ge.L[2]) + ":" +
@@ -575,7 +575,8 @@ int plan_autotune(tl_plan* p) {
           for (int nt : {0, 1})
             for (int flip : {0, 1}) cands.push_back({variant, block, tz, grid, nt, flip, 0});
   }
-  if (!(p->flags & TL_PLAIN) && p->n_steps >= 2 && c->big_lds && !(tl::vprec(p->prec) == tl::F64 && p->width > 1))
+  if (!(p->flags & (TL_PLAIN | TL_ONE_STEP)) && p->n_steps >= 2 && c->big_lds &&
+      !(tl::vprec(p->prec) == tl::F64 && p->width > 1))
     for (int block : {512, 448, 384, 320, 256})
       for (int tz : {4, 8, 16})
         for (int grid : {0, cu})
@@ -1017,7 +1018,8 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
     *out = nullptr;
     if (!jobs || n_jobs < 1) return fail(c, TL_ERR_ARG, "need at least one job");
     if (!valid_prec(prec)) return fail(c, TL_ERR_PRECISION, "unknown precision %d", prec);
-    if (flags & ~(unsigned)(TL_PLAIN | TL_GRAPH | TL_AUTOTUNE)) return fail(c, TL_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if (flags & ~(unsigned)(TL_PLAIN | TL_GRAPH | TL_AUTOTUNE | TL_ONE_STEP))
+      return fail(c, TL_ERR_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & TL_PLAIN) && (flags & TL_GRAPH)) return fail(c, TL_ERR_ARG, "TL_PLAIN runs eager launches; it excludes TL_GRAPH");
     if (n_steps < 0) return fail(c, TL_ERR_ARG, "n_steps = %d is negative", n_steps);
     if (!std::isfinite(sigma)) return fail(c, TL_ERR_ARG, "sigma is not finite");

@@ -1322,7 +1322,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
   for (int mt = 0; mt < sw.n; mt++) {
     const int tile = tile_base + sw.tile(mt);
     const StepGroup& g = groups[find_group(groups, n_groups, tile)];
-    const int Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, k = g.rows;
+    const int Lx = XL ? 64 : g.Lx, Ly = g.Ly, Lz = g.Lz, k = g.rows;   // XL: every row is 64 sites long
     const int64_t Vp = g.Vp;
     const int local = tile - g.tile_begin;
     const int tzi = local / g.n_xy_tiles;          // z chain chunk index: n_z_tiles = chains * chunks
@@ -1388,7 +1388,12 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
     auto link_site = [&](int za, int za1) { return (uint32_t)((up ? za : za1) * LxLy + xy); };
     real ahd[R][6];          // input colour vectors at march position m + 1 (own column)
     real lk[2][18];          // z links (m-1, m) and (m, m+1); step two reloads (m-2, m-1)
-    real mxf[18], mxb[18], myf[18], myb[18];
+    // x two-links: mxf of plane m (step one), mxp of plane m - 1 (step two), which step one's
+    // mxf becomes once both are past their x hops, before the next plane's are loaded into
+    // mxf; mxb, mbp: the backward ones (loaded when rows are not 64 sites long, else taken
+    // from the neighbouring lane)
+    real mxf[18], mxb[18], mxp[18], mbp[18];
+    real myf[18], myb[18];
     // a workgroup with several tiles: every thread has finished reading the previous
     // tile's LDS before its own slots are written
     __syncthreads();
@@ -1429,6 +1434,18 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
     auto stage = [&](auto s2_c, auto more_c) {
       constexpr bool S2 = decltype(s2_c)::value;
       constexpr bool MORE = decltype(more_c)::value;
+      // step one's x two-links become step two's, and the next plane's are loaded
+      auto next_x = [&]() {
+#pragma unroll
+        for (int c = 0; c < 18; c++) mxp[c] = mxf[c];
+        if (!xlane) {
+#pragma unroll
+          for (int c = 0; c < 18; c++) mbp[c] = mxb[c];
+        }
+        const uint32_t zno = (uint32_t)(wrap_sel(zc + step, Lz) * LxLy);
+        PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
+        if (!xlane) PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
+      };
       const int zn = wrap_sel(zc + step, Lz);   // march position m + 1
       const int zb = wrap_sel(zc - step, Lz);   // march position m - 1
       c2* const Ac = (s & 1) ? A1 : A0;          // input plane m; own slots of Ao: plane m - 1
@@ -1470,13 +1487,12 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
         mdv_acc(myb, v, acc[r]);
       }
       __builtin_amdgcn_sched_barrier(0);
-      // in-plane two-links of the next use (step two at plane zb, else step one at plane zn):
-      // x now, y after the z hops
+      // the next plane's x two-links now when no step two runs, else after its x hops; the
+      // y two-links of the next use (step two at plane zb, else step one at plane zn) after
+      // the z hops
+      const uint32_t zno = (uint32_t)(zn * LxLy);
       const uint32_t zon = (uint32_t)((S2 ? zb : zn) * LxLy);
-      if constexpr (S2 || MORE) {
-        PL::load_w_raw(wp[0], zon + (uint32_t)xy, mxf);
-        if (!xlane) PL::load_w_raw(wp[0], zon + (uint32_t)xbw, mxb);
-      }
+      if constexpr (MORE && !S2) next_x();
       {
         real bh[R][6];
 #pragma unroll
@@ -1539,14 +1555,12 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       if constexpr (S2) {
         real l0[18];   // z link (m-2, m-1)
         if (core) PL::load_w(wp[2], link_site(wrap_sel(zb - step, Lz), zb), l0);
-        if (core) {
+        if (core) {   // mxp was completed by step one at the previous stage
           if (xlane) {
             const int src = ((x - D) & 63) * 4;
 #pragma unroll
-            for (int c = 0; c < raw_words(P); c++) mxb[c] = lane_get(mxf[c], src);
+            for (int c = 0; c < 18; c++) mbp[c] = lane_get(mxp[c], src);
           }
-          PL::finish_w(mxf);
-          PL::finish_w(mxb);
 #pragma unroll
           for (int r = 0; r < R; r++) {
 #pragma unroll
@@ -1554,20 +1568,14 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
             real v[6];
 #pragma unroll
             for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
-            mv_acc(mxf, v, acc[r]);
+            mv_acc(mxp, v, acc[r]);
 #pragma unroll
             for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
-            mdv_acc(mxb, v, acc[r]);
+            mdv_acc(mbp, v, acc[r]);
           }
         }
-        // the next stage's step one at plane zn: x two-links as soon as these x hops are done,
-        // y two-links after the y hops
-        const uint32_t zno = (uint32_t)(zn * LxLy);
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (MORE) {
-          PL::load_w_raw(wp[0], zno + (uint32_t)xy, mxf);
-          if (!xlane) PL::load_w_raw(wp[0], zno + (uint32_t)xbw, mxb);
-        }
+        if constexpr (MORE) next_x();
         if (core) {
           PL::finish_w(myf);
           PL::finish_w(myb);

@@ -181,7 +181,8 @@ def test_plan_validation(lib, hctx):
     assert f(hctx, jobs, 1, 10, -1.0, 1, 0, ctypes.byref(out)) == -1
     assert f(hctx, jobs, 1, 10, float("nan"), 1, 0, ctypes.byref(out)) == -1
     assert f(hctx, jobs, 1, 10, 2.0, 4, 0, ctypes.byref(out)) == -3
-    assert f(hctx, jobs, 1, 10, 2.0, 1, 8, ctypes.byref(out)) == -1          # unknown flag
+    assert f(hctx, jobs, 1, 10, 2.0, 1, 8, ctypes.byref(out)) == -4          # TL_ONE_STEP is valid
+    assert f(hctx, jobs, 1, 10, 2.0, 1, 16, ctypes.byref(out)) == -1         # unknown flag
     assert f(hctx, jobs, 1, 10, 2.0, 1, 3, ctypes.byref(out)) == -1          # plain + graph
     assert f(hctx, jobs, 1, 0, 0.0, 1, 0, ctypes.byref(out)) == -4           # zero steps is valid
     j2, keep2 = make_job((4, 4, 4, 4), 2, [0, 2], ws=[0, 1])

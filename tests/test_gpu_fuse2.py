@@ -163,6 +163,15 @@ def test_autotune_includes_two_steps(ctx, orc, torch, monkeypatch):
         assert info["steps_per_launch"] == (2 if info["variant"] == 8 else 1)
         assert np.array_equal(job.psi.cpu().numpy(), ref), n
         plan.close()
+    # TL_ONE_STEP keeps the tuning to one step per launch
+    job = tl.Job(L, ctx.build_twolinks(L, to_dev(U), "f32"), [1, 1, 1], to_dev(psi))
+    plan = ctx.plan([job], 8, 3.0, "f32", tl.TL_AUTOTUNE | tl.TL_ONE_STEP)
+    plan.load()
+    plan.run()
+    plan.store()
+    torch.cuda.synchronize()
+    assert plan.info()["steps_per_launch"] == 1 and plan.info()["variant"] != 8
+    plan.close()
 
 
 def test_two_steps_refusals(ctx, torch, monkeypatch):
