@@ -555,7 +555,9 @@ def main():
                 "traffic_GBs": round(traffic / (step_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
                 "copy_GBs": round(copy_gbs, 1), "ceiling_GBs": ceiling["ceiling_GBs"],
-                "frac_of_ceiling": round(achieved / ceiling["ceiling_GBs"], 4),
+                # the rate of the launch's counted traffic (else of its least bytes) over the best stream
+                "frac_of_ceiling": round((traffic or info["bytes_per_step"]) / (step_ms * 1e-3) / 1e9
+                                         / ceiling["ceiling_GBs"], 4),
                 "ceiling": {k: ceiling[k] for k in ("ceiling_kinds", "step_kinds_GBs", "bytes", "mix", "configs")}}
     log(f"[bench] step kernel ({spl} step(s) per launch) {step_ms * 1e3:.1f} us per launch, "
         f"{achieved:.0f} GB/s algorithmic")
@@ -589,7 +591,7 @@ def main():
     pack_ms = timed(plan.load)
     unpack_ms = timed(plan.store)
     norm_ms = timed(lambda: plan.reduce("norm2"))
-    smear_ms = step_ms * wl.n_steps
+    smear_ms = step_ms * launches
     lat0, U0 = jobs_in[0][0], jobs_in[0][1]
     Wall = links(lat0, U0, prec)
     build_all_ms = timed(lambda: links(lat0, U0, prec, W=Wall), reps=2)
