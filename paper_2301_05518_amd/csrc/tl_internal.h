@@ -102,9 +102,10 @@ inline int fuse_rows(int Lx, int Ly, int D, int block) {
 }
 
 // Dynamic LDS bytes variant 8 needs for a group: two input planes of k + 4 rows and two
-// step-one planes of k + 2 rows of R vectors.
+// step-one planes of k + 2 rows of R vectors (FP32 planes padded to an even entry count).
 inline int64_t lds_bytes_fuse2(int code, int R, int Lx, int k) {
-  return 2LL * (2 * k + 6) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
+  auto plane = [&](int64_t rn) { return vprec(code) == F64 ? 48 * rn : 24 * ((rn + 1) & ~int64_t(1)); };
+  return 2 * (plane((int64_t)R * (k + 4) * Lx) + plane((int64_t)R * (k + 2) * Lx));
 }
 
 // Raise the dynamic-LDS limit of the LDS-staged step kernels (once per device, before any capture).

@@ -1282,6 +1282,38 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
   }
 }
 
+// Colour vectors of one plane of R RHS in LDS, rn = R * slots entries: FP32 as a 16-byte word
+// (colours 0 and 1) and an 8-byte word (colour 2) per entry, each kind in its own array, so a
+// vector is one 128-bit and one 64-bit LDS access; FP64 as three arrays of 16-byte words.
+template <typename real> struct LdsVec;
+template <> struct LdsVec<float> {
+  static __device__ __forceinline__ int bytes(int rn) { return 24 * ((rn + 1) & ~1); }   // 16-byte aligned halves
+  static __device__ __forceinline__ void put(unsigned char* p, int rn, int i, const float (&v)[6]) {
+    reinterpret_cast<v4f*>(p)[i] = v4f{v[0], v[1], v[2], v[3]};
+    reinterpret_cast<v2f*>(p + 16 * ((rn + 1) & ~1))[i] = v2f{v[4], v[5]};
+  }
+  static __device__ __forceinline__ void get(const unsigned char* p, int rn, int i, float (&v)[6]) {
+    const v4f a = reinterpret_cast<const v4f*>(p)[i];
+    const v2f b = reinterpret_cast<const v2f*>(p + 16 * ((rn + 1) & ~1))[i];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+  }
+};
+template <> struct LdsVec<double> {
+  static __device__ __forceinline__ int bytes(int rn) { return 48 * rn; }
+  static __device__ __forceinline__ void put(unsigned char* p, int rn, int i, const double (&v)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) reinterpret_cast<v2d*>(p + 16 * rn * c)[i] = v2d{v[2 * c], v[2 * c + 1]};
+  }
+  static __device__ __forceinline__ void get(const unsigned char* p, int rn, int i, double (&v)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const v2d a = reinterpret_cast<const v2d*>(p + 16 * rn * c)[i];
+      v[2 * c] = a.x;
+      v[2 * c + 1] = a.y;
+    }
+  }
+};
+
 // Variant 8: two smearing steps per launch (temporal blocking).  The second
 // step's input, the first step's output, never leaves the workgroup: each
 // step-one result is rounded to the storage format in registers, exactly as a
@@ -1313,11 +1345,10 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
                                                   typename Fmt<P>::real alpha, typename Fmt<P>::real beta) {
   using PL = Planes<P>;
   using real = typename Fmt<P>::real;
-  using c2 = typename Complex2<real>::type;
+  using LV = LdsVec<real>;
   constexpr int D = hop_of(P);
   constexpr bool xlane = XL && lane_xbw(P);
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  c2* const lds = reinterpret_cast<c2*>(lds_raw);
   const TileSweep sw = xcd_sweep(n_tiles, rev);
   for (int mt = 0; mt < sw.n; mt++) {
     const int tile = tile_base + sw.tile(mt);
@@ -1350,10 +1381,11 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
     const int ybw = lat_row(row - 2) * Lx + x;
     // LDS: input planes (k + 4 rows: chain rows -2 .. k+1), step-one planes (k + 2 rows)
     const int nA = (k + 4) * Lx, nB = (k + 2) * Lx;
-    c2* const A0 = lds;
-    c2* const A1 = A0 + R * 3 * nA;
-    c2* const B0 = A1 + R * 3 * nA;
-    c2* const B1 = B0 + R * 3 * nB;
+    const int rnA = R * nA, rnB = R * nB;
+    unsigned char* const A0 = lds_raw;
+    unsigned char* const A1 = A0 + LV::bytes(rnA);
+    unsigned char* const B0 = A1 + LV::bytes(rnA);
+    unsigned char* const B1 = B0 + LV::bytes(rnB);
     const int xf = wrap_sel(x + D, Lx), xb = wrap_sel(x - D, Lx);
     const int oA = (row + 1) * Lx + x, aXf = (row + 1) * Lx + xf, aXb = (row + 1) * Lx + xb;
     const int aYf = (row + 2) * Lx + x, aYb = row * Lx + x;
@@ -1416,17 +1448,15 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       if (inreg) {
 #pragma unroll
         for (int r = 0; r < R; r++)
-#pragma unroll
-          for (int c = 0; c < 3; c++) {
-            A0[(r * 3 + c) * nA + oA] = c2{cu[r][2 * c], cu[r][2 * c + 1]};
-            A1[(r * 3 + c) * nA + oA] = c2{bh[r][2 * c], bh[r][2 * c + 1]};
+          {
+            LV::put(A0, rnA, r * nA + oA, cu[r]);
+            LV::put(A1, rnA, r * nA + oA, bh[r]);
           }
       }
       if (edge) {
 #pragma unroll
         for (int r = 0; r < R; r++)
-#pragma unroll
-          for (int c = 0; c < 3; c++) A0[(r * 3 + c) * nA + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
+          LV::put(A0, rnA, r * nA + hslot, hv[r]);
       }
     }
     int s = 0;
@@ -1448,10 +1478,10 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       };
       const int zn = wrap_sel(zc + step, Lz);   // march position m + 1
       const int zb = wrap_sel(zc - step, Lz);   // march position m - 1
-      c2* const Ac = (s & 1) ? A1 : A0;          // input plane m; own slots of Ao: plane m - 1
-      c2* const Ao = (s & 1) ? A0 : A1;          // (then plane m + 1, with its outer rows)
-      c2* const Bc = (s & 1) ? B1 : B0;          // own slots: step one at m - 2, then at m
-      c2* const Bo = (s & 1) ? B0 : B1;          // step one at m - 1
+      unsigned char* const Ac = (s & 1) ? A1 : A0;          // input plane m; own slots of Ao: plane m - 1
+      unsigned char* const Ao = (s & 1) ? A0 : A1;          // (then plane m + 1, with its outer rows)
+      unsigned char* const Bc = (s & 1) ? B1 : B0;          // own slots: step one at m - 2, then at m
+      unsigned char* const Bo = (s & 1) ? B0 : B1;          // step one at m - 1
       __syncthreads();
       // ---- step one at plane zc, chain rows -1 .. k
       if (xlane) {
@@ -1469,21 +1499,17 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
 #pragma unroll
         for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
         real v[6];
-#pragma unroll
-        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aXf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        LV::get(Ac, rnA, r * nA + aXf, v);
         mv_acc(mxf, v, acc[r]);
-#pragma unroll
-        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aXb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        LV::get(Ac, rnA, r * nA + aXb, v);
         mdv_acc(mxb, v, acc[r]);
       }
 #pragma unroll
       for (int r = 0; r < R; r++) {
         real v[6];
-#pragma unroll
-        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aYf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        LV::get(Ac, rnA, r * nA + aYf, v);
         mv_acc(myf, v, acc[r]);
-#pragma unroll
-        for (int c = 0; c < 3; c++) { const c2 w = Ac[(r * 3 + c) * nA + aYb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+        LV::get(Ac, rnA, r * nA + aYb, v);
         mdv_acc(myb, v, acc[r]);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1497,8 +1523,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
         real bh[R][6];
 #pragma unroll
         for (int r = 0; r < R; r++)
-#pragma unroll
-          for (int c = 0; c < 3; c++) { const c2 w = Ao[(r * 3 + c) * nA + oA]; bh[r][2 * c] = w.x; bh[r][2 * c + 1] = w.y; }
+          LV::get(Ao, rnA, r * nA + oA, bh[r]);
         if (up) {
 #pragma unroll
           for (int r = 0; r < R; r++) {
@@ -1521,12 +1546,10 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       real s1[R][6];
 #pragma unroll
       for (int r = 0; r < R; r++) {
+        real w[6];
+        LV::get(Ac, rnA, r * nA + oA, w);
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-          const c2 w = Ac[(r * 3 + c) * nA + oA];
-          s1[r][2 * c] = fma_(beta, acc[r][2 * c], alpha * w.x);
-          s1[r][2 * c + 1] = fma_(beta, acc[r][2 * c + 1], alpha * w.y);
-        }
+        for (int c = 0; c < 6; c++) s1[r][c] = fma_(beta, acc[r][c], alpha * w[c]);
         PL::round_v(s1[r]);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1534,8 +1557,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
         if (inreg) {
 #pragma unroll
           for (int r = 0; r < R; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) Ao[(r * 3 + c) * nA + oA] = c2{ahd[r][2 * c], ahd[r][2 * c + 1]};
+            LV::put(Ao, rnA, r * nA + oA, ahd[r]);
         }
       }
       // ---- step two at plane zb, chain rows 0 .. k-1; meanwhile the edge rows load the outer
@@ -1548,8 +1570,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
           for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(zn * LxLy + hxy), hv[r]);
 #pragma unroll
           for (int r = 0; r < R; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) Ao[(r * 3 + c) * nA + hslot] = c2{hv[r][2 * c], hv[r][2 * c + 1]};
+            LV::put(Ao, rnA, r * nA + hslot, hv[r]);
         }
       }
       if constexpr (S2) {
@@ -1566,11 +1587,9 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
 #pragma unroll
             for (int c = 0; c < 6; c++) acc[r][c] = (real)0;
             real v[6];
-#pragma unroll
-            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            LV::get(Bo, rnB, r * nB + bXf, v);
             mv_acc(mxp, v, acc[r]);
-#pragma unroll
-            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bXb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            LV::get(Bo, rnB, r * nB + bXb, v);
             mdv_acc(mbp, v, acc[r]);
           }
         }
@@ -1582,11 +1601,9 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
 #pragma unroll
           for (int r = 0; r < R; r++) {
             real v[6];
-#pragma unroll
-            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bYf]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            LV::get(Bo, rnB, r * nB + bYf, v);
             mv_acc(myf, v, acc[r]);
-#pragma unroll
-            for (int c = 0; c < 3; c++) { const c2 w = Bo[(r * 3 + c) * nB + bYb]; v[2 * c] = w.x; v[2 * c + 1] = w.y; }
+            LV::get(Bo, rnB, r * nB + bYb, v);
             mdv_acc(myb, v, acc[r]);
           }
         }
@@ -1599,8 +1616,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
           real bh[R][6];
 #pragma unroll
           for (int r = 0; r < R; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) { const c2 w = Bc[(r * 3 + c) * nB + oB]; bh[r][2 * c] = w.x; bh[r][2 * c + 1] = w.y; }
+            LV::get(Bc, rnB, r * nB + oB, bh[r]);
           if (up) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
@@ -1618,12 +1634,10 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
 #pragma unroll
           for (int r = 0; r < R; r++) {
             real o[6];
+            real w[6];
+            LV::get(Bo, rnB, r * nB + oB, w);
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-              const c2 w = Bo[(r * 3 + c) * nB + oB];
-              o[2 * c] = fma_(beta, acc[r][2 * c], alpha * w.x);
-              o[2 * c + 1] = fma_(beta, acc[r][2 * c + 1], alpha * w.y);
-            }
+            for (int c = 0; c < 6; c++) o[c] = fma_(beta, acc[r][c], alpha * w[c]);
             if (r < nr) PL::template store_v<real, NT>(op[r], site, o);
           }
         }
@@ -1631,8 +1645,7 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       if (inreg) {   // step one at m: the own slots of Bc (step one at m - 2 is no longer read)
 #pragma unroll
         for (int r = 0; r < R; r++)
-#pragma unroll
-          for (int c = 0; c < 3; c++) Bc[(r * 3 + c) * nB + oB] = c2{s1[r][2 * c], s1[r][2 * c + 1]};
+          LV::put(Bc, rnB, r * nB + oB, s1[r]);
       }
 #pragma unroll
       for (int c = 0; c < 18; c++) lk[0][c] = lk[1][c];
