@@ -1419,7 +1419,8 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
     // z link between march positions a and a + 1: W_z at the lower of their planes
     auto link_site = [&](int za, int za1) { return (uint32_t)((up ? za : za1) * LxLy + xy); };
     real ahd[R][6];          // input colour vectors at march position m + 1 (own column)
-    real lk[2][18];          // z links (m-1, m) and (m, m+1); step two reloads (m-2, m-1)
+    real lk[2][18];          // z links (m-1, m) and (m, m+1)
+    real l0[18];             // z link (m-2, m-1)
     // x two-links: mxf of plane m (step one), mxp of plane m - 1 (step two), which step one's
     // mxf becomes once both are past their x hops, before the next plane's are loaded into
     // mxf; mxb, mbp: the backward ones (loaded when rows are not 64 sites long, else taken
@@ -1514,11 +1515,14 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
       }
       __builtin_amdgcn_sched_barrier(0);
       // the next plane's x two-links now when no step two runs, else after its x hops; the
-      // y two-links of the next use (step two at plane zb, else step one at plane zn) after
-      // the z hops
+      // y two-links of the next use (step two at plane zb, else step one at plane zn) now
       const uint32_t zno = (uint32_t)(zn * LxLy);
       const uint32_t zon = (uint32_t)((S2 ? zb : zn) * LxLy);
       if constexpr (MORE && !S2) next_x();
+      if constexpr (S2 || MORE) {
+        PL::load_w_raw(wp[1], zon + (uint32_t)xy, myf);
+        PL::load_w_raw(wp[1], zon + (uint32_t)ybw, myb);
+      }
       {
         real bh[R][6];
 #pragma unroll
@@ -1537,11 +1541,6 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
             mdv_acc(lk[1], ahd[r], acc[r]);
           }
         }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (S2 || MORE) {
-        PL::load_w_raw(wp[1], zon + (uint32_t)xy, myf);
-        PL::load_w_raw(wp[1], zon + (uint32_t)ybw, myb);
       }
       real s1[R][6];
 #pragma unroll
@@ -1574,8 +1573,6 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
         }
       }
       if constexpr (S2) {
-        real l0[18];   // z link (m-2, m-1)
-        if (core) PL::load_w(wp[2], link_site(wrap_sel(zb - step, Lz), zb), l0);
         if (core) {   // mxp was completed by step one at the previous stage
           if (xlane) {
             const int src = ((x - D) & 63) * 4;
@@ -1648,7 +1645,10 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
           LV::put(Bc, rnB, r * nB + oB, s1[r]);
       }
 #pragma unroll
-      for (int c = 0; c < 18; c++) lk[0][c] = lk[1][c];
+      for (int c = 0; c < 18; c++) {
+        l0[c] = lk[0][c];
+        lk[0][c] = lk[1][c];
+      }
       if constexpr (MORE) {   // the next stage's input plane ahead and its z link
         const int znn = wrap_sel(zn + step, Lz);
 #pragma unroll
