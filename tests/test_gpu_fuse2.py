@@ -186,3 +186,35 @@ def test_two_steps_refusals(ctx, torch, monkeypatch):
         smear(ctx, torch, [(L, U, [0, 0], psi)], 4, 2.0, "f32", tl.TL_PLAIN)
     with pytest.raises(tl.TwolinkError, match="TL_ERR_UNSUPPORTED"):
         smear(ctx, torch, [(L, U, [0, 0], psi)], 4, 2.0, "f64")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "bf16"])
+def test_nan_source_detected_and_confined(ctx, torch, prec, monkeypatch):
+    """A NaN in one source is caught by the plan's FP64 norms and stays in its own RHS: the
+    RHS sharing its two-link loads (same slice, same group) and the RHS of another slice come
+    out bit for bit as without it, under one-step tilings and the two-step kernel."""
+    import paper_2301_05518_amd as tl
+    L = (64, 8, 6, 2)
+    ts = [0, 0, 0, 1]
+    U = synth.gauge_field(L, "haar", 34)
+    psi = synth.random_field(rng(34), (len(ts), 6, 8, 64, 3))
+    bad = psi.copy()
+    bad[1, 3, 2, 17, 1] = complex(np.nan, 0.0)
+    for tile in (DIRECT, "7,512,4,0,1,1", "8,384,3,0,1,1"):
+        monkeypatch.setenv("TL_TILE", tile)
+        outs, norms = [], []
+        for src in (psi, bad):
+            job = tl.Job(L, ctx.build_twolinks(L, to_dev(U), prec), ts, to_dev(src))
+            plan = ctx.plan([job], 6, 2.0, prec, tl.TL_GRAPH)
+            plan.load()
+            plan.run()
+            norms.append(plan.reduce("norm2").cpu().numpy())
+            plan.store()
+            torch.cuda.synchronize()
+            outs.append(job.psi.cpu().numpy())
+            plan.close()
+        log(f"NaN source {prec} tile {tile}: norms {norms[1]}")
+        assert np.isnan(norms[1][1]) and np.isnan(outs[1][1]).any()
+        for r in (0, 2, 3):
+            assert np.isfinite(norms[1][r]) and norms[1][r] == norms[0][r], (tile, r)
+            assert np.array_equal(outs[1][r], outs[0][r]), (tile, r)
