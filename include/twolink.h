@@ -94,7 +94,11 @@ enum { TL_ONELINK = 32 };  /* OR into a precision: a one-link field and the one-
 enum {
     TL_PLAIN = 1u,      /* one right-hand side per launch, RHS in succession, eager launches */
     TL_GRAPH = 2u,      /* capture the n step launches in one HIP graph, replayed per run */
-    TL_AUTOTUNE = 4u,   /* time the candidate tilings once and keep the fastest (cached per context) */
+    TL_AUTOTUNE = 4u,   /* time the candidate tilings once and keep the fastest (cached per context);
+                           for batched plans of two or more steps the candidates include launches
+                           that run two steps each (the first step's result kept on chip, rounded
+                           to the storage precision exactly as a store would round it, so the
+                           result is bit-identical to one step per launch) */
     TL_ONE_STEP = 8u    /* tune over tilings of one step per launch only (no two-step launches) */
 };
 
@@ -277,7 +281,8 @@ int tl_plan_create(tl_ctx *ctx, const tl_job *jobs, int n_jobs, int n_steps, dou
                    int prec, unsigned flags, tl_plan **out);
 /* Pack every job's psi (complex128) into the resident buffer (rounds to the storage precision). */
 int tl_plan_load(tl_plan *plan);
-/* n_steps smearing steps on the resident buffer. */
+/* n_steps smearing steps on the resident buffer (eq. tlSmear applied n_steps times; with a
+   two-step tiling, n_steps / 2 launches plus one one-step launch when n_steps is odd). */
 int tl_plan_run(tl_plan *plan);
 /* Unpack the resident buffer into every job's psi (complex128). */
 int tl_plan_store(tl_plan *plan);
