@@ -109,12 +109,14 @@ def measured_traffic(workload_key: str, tile: str):
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(workload_key)
+        allrec = json.load(open(path))
     except (ValueError, OSError):
         return None
-    if not rec or rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("tile") != tile:
-        return None
-    return rec.get("bytes_per_launch")
+    # a record per tiling ("<workload>|<tile>"); the plain workload key holds the latest one
+    for rec in (allrec.get(f"{workload_key}|{tile}"), allrec.get(workload_key)):
+        if rec and rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("tile") == tile:
+            return rec.get("bytes_per_launch")
+    return None
 
 
 COPY_BYTES = 1 << 30          # known-size device copy used to calibrate the byte counters
@@ -163,6 +165,7 @@ def summarize_counters(fetch_dir, write_dir, workload_key, tile, path=None):
         "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
         "counters": out,
     }
+    allrec[f"{workload_key}|{tile}"] = allrec[workload_key]
     with open(path, "w") as fh:
         json.dump(allrec, fh, indent=1)
     print(json.dumps(allrec[workload_key], indent=1))

@@ -48,6 +48,12 @@ def test_counter_summary(tmp_path):
     assert abs(f["scale"] - 2.0) < 1e-12 and abs(w["scale"] - 1.0) < 1e-12   # small copy ignored
     assert abs(rec["bytes_per_launch"] - (300000 * 1024 * 2.0 + 150000 * 1024)) < 1e-3
     assert json.load(open(out))["workloadX"]["tile"] == "7,512,16,256,1,1"
+    # a second tiling keeps the first one's record under its own key
+    bench.summarize_counters(str(tmp_path / "f"), str(tmp_path / "w"), "workloadX", "8,384,16,256,1,1",
+                             path=str(out))
+    allrec = json.load(open(out))
+    assert allrec["workloadX"]["tile"] == "8,384,16,256,1,1"
+    assert allrec["workloadX|7,512,16,256,1,1"]["tile"] == "7,512,16,256,1,1"
 
 
 def test_accuracy_against_the_oracle():
