@@ -91,21 +91,21 @@ inline int64_t lds_bytes(int code, int R, int Lx, int rows) {
   return 2LL * (rows + 4) * Lx * R * 6 * (vprec(code) == F64 ? 8 : 4);
 }
 
-// Chain rows per tile of variant 8 for an Lx x Ly plane, hop distance D and a block size: the
-// largest k that divides the y chain's length (Ly / 2 for D = 2 and even Ly, else Ly) with
-// (k + 2) * Lx <= block (0 if there is none).
-inline int fuse_rows(int Lx, int Ly, int D, int block) {
-  const int ylen = (D == 2 && !(Ly & 1)) ? Ly / 2 : Ly;
-  for (int k = (block / Lx - 2 < ylen ? block / Lx - 2 : ylen); k >= 1; k--)
-    if (ylen % k == 0) return k;
-  return 0;
-}
-
 // Dynamic LDS bytes variant 8 needs for a group: two input planes of k + 4 rows and two
 // step-one planes of k + 2 rows of R vectors (FP32 planes padded to an even entry count).
 inline int64_t lds_bytes_fuse2(int code, int R, int Lx, int k) {
   auto plane = [&](int64_t rn) { return vprec(code) == F64 ? 48 * rn : 24 * ((rn + 1) & ~int64_t(1)); };
   return 2 * (plane((int64_t)R * (k + 4) * Lx) + plane((int64_t)R * (k + 2) * Lx));
+}
+
+// Chain rows per tile of variant 8 for an Lx x Ly plane of format `code` with R RHS per group
+// and a block size: the largest k that divides the y chain's length (Ly / 2 for two-link hops
+// and even Ly, else Ly) with (k + 2) * Lx <= block and LDS within lds_max (0 if there is none).
+inline int fuse_rows(int code, int R, int Lx, int Ly, int block, int64_t lds_max) {
+  const int ylen = (hop_of(code) == 2 && !(Ly & 1)) ? Ly / 2 : Ly;
+  for (int k = (block / Lx - 2 < ylen ? block / Lx - 2 : ylen); k >= 1; k--)
+    if (ylen % k == 0 && lds_bytes_fuse2(code, R, Lx, k) <= lds_max) return k;
+  return 0;
 }
 
 // Raise the dynamic-LDS limit of the LDS-staged step kernels (once per device, before any capture).

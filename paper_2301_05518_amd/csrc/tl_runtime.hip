@@ -392,7 +392,8 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
     s.nr = gr.nr;
     if (cfg.variant == 8) {   // two steps per launch: blocks of k rows of one y chain
       const int D = tl::hop_of(p->prec);
-      s.rows = tl::fuse_rows(g.L[0], g.L[1], D, cfg.block);
+      const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
+      s.rows = tl::fuse_rows(p->prec, R, g.L[0], g.L[1], cfg.block, 160 * 1024);
       if (s.rows == 0) return TL_ERR_UNSUPPORTED;
       const int ychains = (D == 2 && !(g.L[1] & 1)) ? 2 : 1;
       s.n_xy_tiles = ychains * (g.L[1] / ychains / s.rows);

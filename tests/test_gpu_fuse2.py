@@ -96,6 +96,41 @@ def test_two_steps_bit_identical(ctx, orc, torch, prec, n, monkeypatch):
         assert mr < tol(prec, n) and l2 < tol(prec, n), L
 
 
+# every lattice with rows of 64 sites: the kernel built for that row length (backward x
+# two-links from the neighbouring lane where the form allows it)
+ROW64_CASES = [((64, 8, 6, 2), [0, 0, 1, 0]), ((64, 6, 5, 1), [0, 0, 0]), ((64, 2, 4, 1), [0])]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16", "f32-w12", "f16s-w12", "f32-onelink",
+                                  "f16s-onelink"])
+def test_two_steps_rows_of_64(ctx, orc, torch, prec, monkeypatch):
+    lats = []
+    for k, (L, ts) in enumerate(ROW64_CASES):
+        if prec.startswith("f64"):
+            ts = sorted(set(ts))
+        U = synth.gauge_field(L, "haar", 40 + k)
+        psi = synth.random_field(rng(40 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+    n, sigma = (5, 0.5) if prec.endswith("-onelink") else (7, 2.5)
+    monkeypatch.setenv("TL_TILE", DIRECT)
+    ref = smear(ctx, torch, lats, n, sigma, prec, variant=0)
+    for tile in ("8,512,4,0", "8,384,3,0,1,1", "8,192,1,8,0,1", "8,448,16,5,1,0"):
+        monkeypatch.setenv("TL_TILE", tile)
+        log(f"two steps per launch, rows of 64, {prec}: tile {tile}")
+        out = smear(ctx, torch, lats, n, sigma, prec, variant=8)
+        for (L, _, _, _), a, b in zip(lats, out, ref):
+            assert np.array_equal(a, b), (tile, L)
+    for (L, U, ts, psi), o in zip(lats, ref):
+        if prec.endswith("-onelink"):
+            r = orc.smear_onelink_batch(U, ts, n, sigma, psi)
+            base = prec.replace("-onelink", "")
+        else:
+            r = orc.smear_batch(orc.build_twolinks(U), ts, n, sigma, psi)
+            base = prec
+        mr, l2 = errors(o, r)
+        assert mr < tol(base, n) and l2 < tol(base, n), L
+
+
 @pytest.mark.parametrize("prec", ["f32-onelink", "f16s-onelink"])
 def test_two_steps_onelink(ctx, orc, torch, prec, monkeypatch):
     """One-link fields (hops of one site): the chains are all rows and all planes."""
