@@ -556,6 +556,7 @@ def main():
                 # and the share of HBM bandwidth the launch's counted traffic uses
                 "launch_min_bytes": info["bytes_per_step"],
                 "traffic_GBs": round(traffic / (step_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "traffic_frac": round(traffic / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "avg_launch_ms": round(step_ms, 5), "isolated_launch_ms": round(isolated_ms, 5),
                 "copy_GBs": round(copy_gbs, 1), "ceiling_GBs": ceiling["ceiling_GBs"],
                 # the rate of the launch's counted traffic (else of its least bytes) over the best stream
