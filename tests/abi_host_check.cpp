@@ -73,7 +73,8 @@ int main() {
   expect(tl_plan_create(c, jobs, 1, 10, 7.0, TL_F32, 0, &p), TL_ERR_ARG, "plan sigma/n > 2/3");
   expect(tl_plan_create(c, jobs, 1, 12, 2.0, TL_F32 | TL_ONELINK, 0, &p), TL_ERR_DEVICE, "one-link plan valid");
   expect(tl_plan_create(c, jobs, 1, 10, 2.0, TL_F32 | TL_ONELINK, 0, &p), TL_ERR_ARG, "one-link sigma/n > 1/6");
-  expect(tl_plan_create(c, jobs, 1, 10, 2.0, TL_F32, 8, &p), TL_ERR_ARG, "plan unknown flag");
+  expect(tl_plan_create(c, jobs, 1, 10, 2.0, TL_F32, 16, &p), TL_ERR_ARG, "plan unknown flag");
+  expect(tl_plan_create(c, jobs, 1, 10, 2.0, TL_F32, TL_ONE_STEP | TL_AUTOTUNE, &p), TL_ERR_DEVICE, "one-step flag valid");
   expect(tl_plan_create(c, jobs, 1, 10, 2.0, TL_F32, TL_PLAIN | TL_GRAPH, &p), TL_ERR_ARG, "plain with graph");
   expect(tl_plan_create(c, jobs, 2, 10, 2.0, TL_F32, 0, &p), TL_ERR_SHAPE, "RHS slice not in W");
   ts2[1] = 1;
