@@ -1558,6 +1558,9 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
           for (int r = 0; r < R; r++)
             LV::put(Ao, rnA, r * nA + oA, ahd[r]);
         }
+        const int znn = wrap_sel(zn + step, Lz);   // the next stage's input plane ahead
+#pragma unroll
+        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(znn * LxLy + xy), ahd[r]);
       }
       // ---- step two at plane zb, chain rows 0 .. k-1; meanwhile the edge rows load the outer
       // rows of input plane m + 1 into Ao (whose outer rows were last read before this
@@ -1649,11 +1652,8 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
         l0[c] = lk[0][c];
         lk[0][c] = lk[1][c];
       }
-      if constexpr (MORE) {   // the next stage's input plane ahead and its z link
-        const int znn = wrap_sel(zn + step, Lz);
-#pragma unroll
-        for (int r = 0; r < R; r++) PL::load_v(ip[r], (uint32_t)(znn * LxLy + xy), ahd[r]);
-        PL::load_w(wp[2], link_site(zn, znn), lk[1]);
+      if constexpr (MORE) {   // the next stage's z link
+        PL::load_w(wp[2], link_site(zn, wrap_sel(zn + step, Lz)), lk[1]);
       }
       zc = zn;
       s++;
