@@ -300,6 +300,19 @@ def compact_lattice(lat):
     return L, U, [slices.index(t) for t in lat.t_of_rhs]
 
 
+TILE_KEYS = ("variant", "block", "tz", "grid", "nt", "flip")
+
+
+def tile_text(info) -> str:
+    """A plan's tiling as TL_TILE reads it (the RHS-per-group field when groups are split)."""
+    t = ",".join(str(info[k]) for k in TILE_KEYS)
+    return t + (f",{info['tile_width']}" if info["tile_width"] != info["group_width"] else "")
+
+
+def tile_dict(info) -> dict:
+    return {**{k: info[k] for k in TILE_KEYS}, "width": info["tile_width"]}
+
+
 KERNEL_NAMES = ["step_direct", "step_zmarch", "step_zring", "step_zfront", "step_rolled", "step_zlds", "step_zchain",
                 "step_zpipe", "step_fuse2"]
 
@@ -362,7 +375,7 @@ def measure_workload(ctx, torch, tl, dev, index, prec, plain=False, passes=5):
            "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
            "working_set_MB": round(info["bytes_per_step"] / 1e6, 1),
            "max_rel": mr, "l2_rel": l2,
-           "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip")}}
+           "tile": tile_dict(info)}
     plan.close()
     if plain:
         pj = [tl.Job(L, ctx.build_twolinks(L, Ud, "f64"), ts, psi) for L, Ud, ts, psi in jobs]
@@ -546,7 +559,7 @@ def main():
     algo_bytes = info["bytes_per_step"] * spl
     achieved = algo_bytes / (step_ms * 1e-3) / 1e9
     key = workload_key(args)
-    tile = ",".join(str(info[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))
+    tile = tile_text(info)
     traffic = measured_traffic(key, tile)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -574,7 +587,7 @@ def main():
         a1 = i1["bytes_per_step"] / (ms1 * 1e-3) / 1e9
         roofline["one_step"] = {"kernel": KERNEL_NAMES[i1["variant"]], "launch_ms": round(ms1, 5),
                                 "achieved": round(a1, 1), "frac": round(a1 / HBM_PEAK_GBS, 4),
-                                "tile": ",".join(str(i1[k]) for k in ("variant", "block", "tz", "grid", "nt", "flip"))}
+                                "tile": tile_text(i1)}
         p1.close()
         log(f"[bench] fastest one-step tiling: {roofline['one_step']}")
 
@@ -623,7 +636,7 @@ def main():
         plain_rate = pinfo["rhs_sites"] * wl.n_steps / (plain_ms * 1e-3)
         plain = {"smear_ms": round(plain_ms, 3), "rate": plain_rate,
                  "launch_us": round(launch_ms * 1e3, 2),
-                 "tile": {k: pinfo[k] for k in ("variant", "block", "tz", "grid", "nt", "flip")},
+                 "tile": tile_dict(pinfo),
                  "achieved_GBs": round(pinfo["bytes_per_step"] / (plain_ms / wl.n_steps * 1e-3) / 1e9, 1),
                  "speedup_of_batched": round(smear_rate / plain_rate, 3)}
         p64.close()
@@ -647,7 +660,7 @@ def main():
                "achieved_GBs": round(winfo["bytes_per_step"] / (w_ms * 1e-3) / 1e9, 1),
                "frac": round(winfo["bytes_per_step"] / (w_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "smear_only_rate": winfo["rhs_sites"] / (w_ms * 1e-3),
-               "tile": {k: winfo[k] for k in ("variant", "block", "tz", "grid", "nt", "flip")}}
+               "tile": tile_dict(winfo)}
         pw.close()
         del wjobs
         torch.cuda.empty_cache()
@@ -700,7 +713,7 @@ def main():
             "accumulate": "f64" if base == "f64" else "f32",
             "operator": "one-link Laplacian H - 6" if args.onelink else "two-link Laplacian (eq. tlLapl1)",
             "pass": "build(source slices) + pack + n steps + FP64 norms + unpack",
-            "tile": {k: info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip", "n_tiles", "group_width")},
+            "tile": {**tile_dict(info), "n_tiles": info["n_tiles"], "group_width": info["group_width"]},
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

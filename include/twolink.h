@@ -152,6 +152,8 @@ typedef struct {
     int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN */
     int32_t steps_per_launch;  /* 2 when each launch runs two steps (variant 8; an odd step count
                                   ends with one launch of a one-step tiling), else 1 */
+    int32_t tile_width;        /* RHS per step group in the launches: group_width, or 1 when the
+                                  tuned tiling gives every RHS its own tiles */
     int64_t rhs_sites;         /* sum over RHS of Lx*Ly*Lz */
     double bytes_per_step;     /* algorithmic bytes of one step: W once per group + psi in and out */
     double flops_per_step;     /* 444 per RHS-site-update */

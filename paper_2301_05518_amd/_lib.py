@@ -55,7 +55,7 @@ class PlanInfo(ctypes.Structure):
         ("n_groups", ctypes.c_int32), ("group_width", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
         ("variant", ctypes.c_int32), ("block", ctypes.c_int32), ("tz", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("nt", ctypes.c_int32), ("flip", ctypes.c_int32),
-        ("launches_per_step", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
+        ("launches_per_step", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32), ("tile_width", ctypes.c_int32),
         ("rhs_sites", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
         ("flops_per_step", ctypes.c_double), ("resident_bytes", ctypes.c_int64),
     ]

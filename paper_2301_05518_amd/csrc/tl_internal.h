@@ -76,6 +76,9 @@ struct StepConfig {
                  // still in the Infinity Cache when a step's working set exceeds it
   int rev;       // set per launch: this launch runs reversed
   int rows64;    // variant 8, set with the work list: every group's rows are 64 sites long
+  int width;     // RHS per step group in the work list (0: the plan's groups, up to four RHS of a
+                 // slice sharing each two-link load; 1: every RHS its own tiles, more parallel
+                 // work for small lattices, the two-links loaded once per RHS)
 };
 
 // Rows per tile of variants 5-7 for an Lx x Ly plane and a block size: the largest divisor of Ly

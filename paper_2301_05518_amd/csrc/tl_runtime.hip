@@ -229,43 +229,58 @@ double max_step(bool one) { return one ? 1.0 / 6.0 : 2.0 / 3.0; }
 // A step configuration a cache entry or TL_TILE may name.
 bool valid_cfg(const StepConfig& g) {
   return g.variant >= 0 && g.variant <= 8 && g.block >= 64 && g.block <= (g.variant >= 5 ? 512 : 256) &&
-         g.block % 64 == 0 && g.tz >= 1 && (g.nt == 0 || g.nt == 1) && (g.flip == 0 || g.flip == 1);
+         g.block % 64 == 0 && g.tz >= 1 && (g.nt == 0 || g.nt == 1) && (g.flip == 0 || g.flip == 1) &&
+         g.width >= 0 && g.width <= 4;
 }
 
-// "variant,block,tz,grid,nt,flip" with an optional ";variant,block,tz,grid,nt,flip" naming the
-// one-step tiling of a two-step one; n_min: fields the first part needs (the rest default to 0).
+// Up to 7 comma-separated integers "variant,block,tz,grid,nt,flip,width" at v into c (missing
+// ones 0); returns how many were read and sets *end past them.
+int parse_cfg(const char* v, StepConfig* c, const char** end) {
+  int* f[7] = {&c->variant, &c->block, &c->tz, &c->grid, &c->nt, &c->flip, &c->width};
+  *c = StepConfig{};
+  int n = 0;
+  const char* q = v;
+  while (n < 7) {
+    char* e = nullptr;
+    const long x = strtol(q, &e, 10);
+    if (e == q || x < -(1L << 30) || x > (1L << 30)) break;
+    *f[n++] = (int)x;
+    q = e;
+    if (*q != ',') break;
+    q++;
+  }
+  *end = q;
+  return n;
+}
+
+// "variant,block,tz,grid[,nt[,flip[,width]]]" with an optional ";..." naming the one-step tiling
+// of a two-step one (six or seven fields); n_min: fields the first part needs.
 bool parse_tuned(const char* v, int n_min, Tuned* out) {
   Tuned t;
-  StepConfig& c = t.cfg;
-  c = StepConfig{0, 0, 0, 0, 0, 0, 0};
-  int used = 0;
-  const int n = sscanf(v, "%d,%d,%d,%d,%d,%d%n", &c.variant, &c.block, &c.tz, &c.grid, &c.nt, &c.flip, &used);
-  if (n < n_min) return false;
-  if (n < 6) {   // fewer fields: no companion, and nt/flip as given or 0
-    if (n < 5) c.nt = 0;
-    c.flip = 0;
-    used = 0;
-  }
-  if (!valid_cfg(c)) return false;
-  if (n == 6 && v[used] == ';') {
-    StepConfig& d = t.single;
-    d = StepConfig{0, 0, 0, 0, 0, 0, 0};
-    if (sscanf(v + used + 1, "%d,%d,%d,%d,%d,%d", &d.variant, &d.block, &d.tz, &d.grid, &d.nt, &d.flip) != 6 ||
-        !valid_cfg(d) || d.variant == 8)
+  const char* end = nullptr;
+  const int n = parse_cfg(v, &t.cfg, &end);
+  if (n < n_min || !valid_cfg(t.cfg)) return false;
+  if (*end == ';') {
+    if (n < 6 || parse_cfg(end + 1, &t.single, &end) < 6 || *end != '\0' || !valid_cfg(t.single) ||
+        t.single.variant == 8)
       return false;
+  } else if (*end != '\0') {
+    return false;
   }
-  if (c.variant == 8 && t.single.variant < 0) t.single = StepConfig{0, 256, 4, 0, 0, 0, 0};
+  if (t.cfg.variant != 8) t.single = StepConfig{-1, 0, 0, 0, 0, 0, 0};
+  else if (t.single.variant < 0) t.single = StepConfig{0, 256, 4, 0, 0, 0, 0};
   *out = t;
   return true;
 }
 
 std::string cfg_text(const StepConfig& g) {
   return std::to_string(g.variant) + "," + std::to_string(g.block) + "," + std::to_string(g.tz) + "," +
-         std::to_string(g.grid) + "," + std::to_string(g.nt) + "," + std::to_string(g.flip);
+         std::to_string(g.grid) + "," + std::to_string(g.nt) + "," + std::to_string(g.flip) +
+         (g.width > 0 ? "," + std::to_string(g.width) : std::string());
 }
 
-// Tuning cache file (TL_TUNE_CACHE): a JSON object {"<workload key>": "variant,block,tz,grid,nt,flip", ...}
-// (a two-step tiling followed by ";" and its one-step companion).  The keys (architecture,
+// Tuning cache file (TL_TUNE_CACHE): a JSON object {"<workload key>": "variant,block,tz,grid,nt,flip[,width]",
+// ...} (a two-step tiling followed by ";" and its one-step companion).  The keys (architecture,
 // precision code, group width, launch mode, each group's dims and RHS) hold no quote or
 // backslash, so the file is read and written with plain string handling; a missing,
 // unreadable or malformed file is an empty cache.
@@ -344,8 +359,10 @@ struct tl_plan {
   char* buf[2] = {nullptr, nullptr};
   int cur = 0;
 
-  // device tables: the step groups of both tilings, per-job pack offsets, reduction fields, partials
+  // device tables: the step groups of both tilings (group_cap entries each), per-job pack
+  // offsets, reduction fields, partials
   char* tables = nullptr;
+  size_t group_cap = 0;
   int64_t* packoff_dev = nullptr;
   std::vector<int64_t> packoff_first;   // index of job j's first entry in packoff_dev
   tl::RedField* red_dev = nullptr;
@@ -372,51 +389,60 @@ struct tl_plan {
 
 namespace {
 
+// RHS per step group of a configuration: the plan's groups, or narrower ones (cfg.width).
+int eff_width(const tl_plan* p, const StepConfig& cfg) {
+  return cfg.width > 0 ? std::min(cfg.width, p->width) : p->width;
+}
+
 // Work list of a plan for one step configuration.
 int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>* out) {
   out->clear();
   int tiles = 0;
-  for (const auto& gr : p->groups) {
-    const auto& jc = p->jobs[gr.job];
-    const tl_geom& g = jc.job.g;
-    StepGroup s{};
-    const int64_t wslot = (int64_t)gr.slot * 3 * jc.Vp * tl::kWBytes[p->prec];
-    s.W = static_cast<const char*>(jc.job.W) + wslot;
-    s.w_mu_stride = jc.Vp * tl::kWBytes[p->prec];
-    s.psi_off = p->res[gr.first].off;
-    s.rhs_stride = gr.nr > 1 ? p->res[gr.first + 1].off - p->res[gr.first].off : 0;
-    s.Lx = g.L[0];
-    s.Ly = g.L[1];
-    s.Lz = g.L[2];
-    s.Vp = (int32_t)jc.Vp;
-    s.nr = gr.nr;
-    if (cfg.variant == 8) {   // two steps per launch: blocks of k rows of one y chain
-      const int D = tl::hop_of(p->prec);
-      const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
-      s.rows = tl::fuse_rows(p->prec, R, g.L[0], g.L[1], cfg.block, 160 * 1024);
-      if (s.rows == 0) return TL_ERR_UNSUPPORTED;
-      const int ychains = (D == 2 && !(g.L[1] & 1)) ? 2 : 1;
-      s.n_xy_tiles = ychains * (g.L[1] / ychains / s.rows);
-    } else if (cfg.variant >= 5) {   // full-row tiles
-      s.rows = tl::lds_rows(g.L[0], g.L[1], cfg.block);
-      if (s.rows == 0) return TL_ERR_UNSUPPORTED;
-      s.n_xy_tiles = g.L[1] / s.rows;
-    } else {
-      s.rows = 0;
-      s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
+  const int ew = eff_width(p, cfg);
+  for (const auto& gr0 : p->groups) {
+    for (int first = gr0.first; first < gr0.first + gr0.nr; first += ew) {   // the plan's group, or its parts
+      const auto& jc = p->jobs[gr0.job];
+      const tl_geom& g = jc.job.g;
+      const int nr = std::min(ew, gr0.first + gr0.nr - first);
+      StepGroup s{};
+      const int64_t wslot = (int64_t)gr0.slot * 3 * jc.Vp * tl::kWBytes[p->prec];
+      s.W = static_cast<const char*>(jc.job.W) + wslot;
+      s.w_mu_stride = jc.Vp * tl::kWBytes[p->prec];
+      s.psi_off = p->res[first].off;
+      s.rhs_stride = nr > 1 ? p->res[first + 1].off - p->res[first].off : 0;
+      s.Lx = g.L[0];
+      s.Ly = g.L[1];
+      s.Lz = g.L[2];
+      s.Vp = (int32_t)jc.Vp;
+      s.nr = nr;
+      if (cfg.variant == 8) {   // two steps per launch: blocks of k rows of one y chain
+        const int D = tl::hop_of(p->prec);
+        const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : ew;
+        s.rows = tl::fuse_rows(p->prec, R, g.L[0], g.L[1], cfg.block, 160 * 1024);
+        if (s.rows == 0) return TL_ERR_UNSUPPORTED;
+        const int ychains = (D == 2 && !(g.L[1] & 1)) ? 2 : 1;
+        s.n_xy_tiles = ychains * (g.L[1] / ychains / s.rows);
+      } else if (cfg.variant >= 5) {   // full-row tiles
+        s.rows = tl::lds_rows(g.L[0], g.L[1], cfg.block);
+        if (s.rows == 0) return TL_ERR_UNSUPPORTED;
+        s.n_xy_tiles = g.L[1] / s.rows;
+      } else {
+        s.rows = 0;
+        s.n_xy_tiles = (int32_t)(((int64_t)g.L[0] * g.L[1] + cfg.block - 1) / cfg.block);
+      }
+      if (cfg.variant >= 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd (and for
+        const int chains = (tl::is_one(p->prec) || (g.L[2] & 1)) ? 1 : 2;   // one-links: consecutive planes)
+        const int clen = g.L[2] / chains;
+        s.n_z_tiles = chains * ((clen + cfg.tz - 1) / cfg.tz);
+      } else {
+        s.n_z_tiles = (g.L[2] + cfg.tz - 1) / cfg.tz;
+      }
+      s.tile_begin = tiles;
+      const int64_t nt = (int64_t)s.n_xy_tiles * s.n_z_tiles;
+      if (tiles + nt > (int64_t)1 << 30) return TL_ERR_UNSUPPORTED;
+      tiles += (int)nt;
+      out->push_back(s);
     }
-    if (cfg.variant >= 6) {   // chains of planes z, z+2, ...: two for even Lz, one for odd (and for
-      const int chains = (tl::is_one(p->prec) || (g.L[2] & 1)) ? 1 : 2;   // one-links: consecutive planes)
-      const int clen = g.L[2] / chains;
-      s.n_z_tiles = chains * ((clen + cfg.tz - 1) / cfg.tz);
-    } else {
-      s.n_z_tiles = (g.L[2] + cfg.tz - 1) / cfg.tz;
-    }
-    s.tile_begin = tiles;
-    const int64_t nt = (int64_t)s.n_xy_tiles * s.n_z_tiles;
-    if (tiles + nt > (int64_t)1 << 30) return TL_ERR_UNSUPPORTED;
-    tiles += (int)nt;
-    out->push_back(s);
   }
   return TL_OK;
 }
@@ -425,7 +451,7 @@ int make_groups(const tl_plan* p, const StepConfig& cfg, std::vector<StepGroup>*
 int64_t plan_lds(const tl_plan* p, const StepConfig& cfg, const std::vector<StepGroup>& gs) {
   if (cfg.variant < 5) return 0;
   int64_t mx = 0;
-  const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : p->width;
+  const int R = (tl::vprec(p->prec) == tl::F64) ? 1 : eff_width(p, cfg);
   for (const auto& g : gs)
     mx = std::max(mx, cfg.variant == 8 ? tl::lds_bytes_fuse2(p->prec, R, g.Lx, g.rows)
                                        : tl::lds_bytes(p->prec, R, g.Lx, g.rows));
@@ -438,7 +464,7 @@ bool tiling_applies(const tl_plan* p, const StepConfig& cfg, const char** reason
     *reason = "one-link smearing runs the step variants 0, 4, 7 and 8 only";
     return false;
   }
-  if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && p->width > 1) {
+  if (cfg.variant >= 5 && tl::vprec(p->prec) == tl::F64 && eff_width(p, cfg) > 1) {
     *reason = "the LDS-staged step kernels take FP64 groups of one RHS only";
     return false;
   }
@@ -465,6 +491,8 @@ int upload_tiling(tl_plan* p, const StepConfig& cfg, tl_plan::Tiling* t) {
   if (!tiling_applies(p, cfg, &why)) return fail(p->ctx, TL_ERR_UNSUPPORTED, "%s", why);
   std::vector<StepGroup> gs;
   (void)make_groups(p, cfg, &gs);
+  if (gs.size() > p->group_cap)   // the device table holds one entry per RHS at most
+    return fail(p->ctx, TL_ERR_UNSUPPORTED, "work list of %zu groups exceeds the table (%zu)", gs.size(), p->group_cap);
   TL_TRY(upload(p->ctx, t->dev, gs.data(), gs.size() * sizeof(StepGroup)));
   t->cfg = cfg;
   t->cfg.rows64 = std::all_of(gs.begin(), gs.end(), [](const StepGroup& g) { return g.Lx == 64; }) ? 1 : 0;
@@ -494,7 +522,7 @@ int plan_launch(tl_plan* p, const tl_plan::Tiling& t, hipStream_t s, const char*
   StepConfig cfg = t.cfg;
   cfg.rev = (cfg.flip && (k & 1)) ? 1 : 0;
   return launch(c, "smearing step", [&] {
-    return tl::launch_step(p->prec, p->width, cfg, t.dev, (int)t.host.size(), base, n, in, out, p->alpha, p->beta,
+    return tl::launch_step(p->prec, eff_width(p, cfg), cfg, t.dev, (int)t.host.size(), base, n, in, out, p->alpha, p->beta,
                            t.lds, s);
   });
 }
@@ -562,20 +590,30 @@ int plan_autotune(tl_plan* p) {
   c->stats.tune_sweeps++;
   std::vector<StepConfig> cands, cands2;
   const int cu = std::max(c->n_cu, 1);
-  for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
-    const bool lds_variant = variant >= 5;
-    if (tl::is_one(p->prec) && variant != 0 && variant != 4 && variant != 7) continue;   // one-link: hops of one site
-    if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && p->width > 1) continue;   // would run variant 0
-    if (lds_variant && !c->big_lds) continue;
-    const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
-                                 : (variant >= 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
-    const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 128, 64};
-    for (int block : blocks)
-      for (int tz : tzs)
-        for (int grid : {0, cu, 8 * cu})   // one workgroup per tile, or persistent: 1 or 8 per CU
-          for (int nt : {0, 1})
-            for (int flip : {0, 1}) cands.push_back({variant, block, tz, grid, nt, flip, 0});
-  }
+  // the plan's RHS groups, and (batched plans with wider groups) every RHS on its own tiles:
+  // more parallel work for small lattices at the price of loading each two-link once per RHS
+  std::vector<int> widths{0};
+  if (!(p->flags & TL_PLAIN) && p->width > 1) widths.push_back(1);
+  for (int wd : widths)
+    for (int variant : {0, 2, 3, 4, 5, 6, 7}) {
+      const bool lds_variant = variant >= 5;
+      const int ew = wd > 0 ? wd : p->width;
+      if (tl::is_one(p->prec) && variant != 0 && variant != 4 && variant != 7) continue;   // one-link: hops of one site
+      if ((variant == 2 || variant == 3 || lds_variant) && tl::vprec(p->prec) == tl::F64 && ew > 1) continue;   // would run variant 0
+      if (lds_variant && !c->big_lds) continue;
+      const std::vector<int> tzs = (variant == 0 || variant == 4) ? std::vector<int>{1, 2, 4}
+                                   : (variant >= 6 ? std::vector<int>{4, 8, 16} : std::vector<int>{8, 16, 32});
+      const std::vector<int> blocks = lds_variant ? std::vector<int>{512, 256} : std::vector<int>{256, 128, 64};
+      for (int block : blocks)
+        for (int tz : tzs)
+          for (int grid : {0, cu, 8 * cu})   // one workgroup per tile, or persistent: 1 or 8 per CU
+            for (int nt : {0, 1})
+              for (int flip : {0, 1}) {
+                StepConfig g{variant, block, tz, grid, nt, flip, 0};
+                g.width = wd;
+                cands.push_back(g);
+              }
+    }
   if (!(p->flags & (TL_PLAIN | TL_ONE_STEP)) && p->n_steps >= 2 && c->big_lds &&
       !(tl::vprec(p->prec) == tl::F64 && p->width > 1))
     for (int block : {512, 448, 384, 320, 256})
@@ -624,8 +662,8 @@ int plan_autotune(tl_plan* p) {
   };
   auto log = [&](const StepConfig& g, float ms_step, bool same) {
     if (c->log)
-      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d flip=%d: %.4f ms/step%s\n",
-              key.c_str(), g.variant, g.block, g.tz, g.grid, g.nt, g.flip, ms_step,
+      fprintf(stderr, "[twolink] tune %s variant=%d block=%d tz=%d grid=%d nt=%d flip=%d width=%d: %.4f ms/step%s\n",
+              key.c_str(), g.variant, g.block, g.tz, g.grid, g.nt, g.flip, eff_width(p, g), ms_step,
               same ? "" : "  OUTPUT DIFFERS - rejected");
   };
   float best = 1e30f;
@@ -1105,7 +1143,9 @@ int tl_plan_create(tl_ctx* c, const tl_job* jobs, int n_jobs, int n_steps, doubl
       p->buf[k] = static_cast<char*>(b);
     }
     const size_t n_res = p->res.size();
-    const size_t gbytes = 2 * align256(p->groups.size() * sizeof(StepGroup));   // two tilings
+    // two tilings' step groups: a tiling may split the plan's groups down to one RHS each
+    p->group_cap = n_res;
+    const size_t gbytes = 2 * align256(n_res * sizeof(StepGroup));
     const size_t obytes = align256(n_res * sizeof(int64_t));
     const size_t rbytes = align256(n_res * sizeof(tl::RedField));
     const size_t pbytes = align256((size_t)tl::red_partials_doubles((int)n_res, p->max_v3) * sizeof(double));
@@ -1329,6 +1369,7 @@ int tl_plan_get_info(const tl_plan* p, tl_plan_info* info) {
     info->nt = t.cfg.nt;
     info->flip = t.cfg.flip;
     info->steps_per_launch = t.cfg.variant == 8 ? 2 : 1;
+    info->tile_width = eff_width(p, t.cfg);
     return TL_OK;
   } catch (...) {
     return host_failure(p ? p->ctx : nullptr);

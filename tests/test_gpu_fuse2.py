@@ -253,3 +253,48 @@ def test_nan_source_detected_and_confined(ctx, torch, prec, monkeypatch):
         for r in (0, 2, 3):
             assert np.isfinite(norms[1][r]) and norms[1][r] == norms[0][r], (tile, r)
             assert np.array_equal(outs[1][r], outs[0][r]), (tile, r)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_split_groups_bit_identical(ctx, orc, torch, prec, monkeypatch):
+    """Tilings that give every RHS its own tiles (TL_TILE width field 1: the slice's two-links
+    loaded once per RHS) compute the same bits as the plan's groups of up to four RHS; FP64,
+    whose LDS-staged kernels take one RHS per group, runs them on split groups."""
+    import paper_2301_05518_amd as tl
+    L1, L2 = (64, 8, 6, 2), (10, 6, 7, 2)
+    lats = []
+    for k, (L, ts) in enumerate(((L1, [0, 0, 0, 1, 1]), (L2, [1, 1, 1, 1]))):
+        U = synth.gauge_field(L, "haar", 50 + k)
+        psi = synth.random_field(rng(50 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+    monkeypatch.setenv("TL_TILE", DIRECT)
+    ref = smear(ctx, torch, lats, 6, 2.0, prec, variant=0)
+    tiles = ["0,64,1,0,0,0,1", "4,128,2,3,1,1,1", "7,512,4,0,1,1,1", "5,256,3,0,0,0,1"]
+    if prec != "f64":
+        tiles += ["8,384,3,0,1,1,1", "8,384,3,0,1,1,2"]
+    for tile in tiles:
+        monkeypatch.setenv("TL_TILE", tile)
+        log(f"split groups {prec}: tile {tile}")
+        job_out = smear(ctx, torch, lats, 6, 2.0, prec, variant=int(tile[0]))
+        for (L, _, _, _), a, b in zip(lats, job_out, ref):
+            assert np.array_equal(a, b), (tile, L)
+    for (L, U, ts, psi), o in zip(lats, ref):
+        mr, l2 = errors(o, orc.smear_batch(orc.build_twolinks(U), ts, 6, 2.0, psi))
+        assert mr < tol(prec, 6) and l2 < tol(prec, 6), L
+
+
+def test_plan_info_reports_split_width(ctx, torch, monkeypatch):
+    import paper_2301_05518_amd as tl
+    L = (12, 8, 6, 1)
+    U = synth.gauge_field(L, "haar", 52)
+    psi = synth.random_field(rng(52), (3, 6, 8, 12, 3))
+    for tile, w in (("4,128,2,0,0,0,1", 1), ("4,128,2,0,0,0", 3)):
+        monkeypatch.setenv("TL_TILE", tile)
+        job = tl.Job(L, ctx.build_twolinks(L, to_dev(U), "f32"), [0, 0, 0], to_dev(psi))
+        plan = ctx.plan([job], 4, 1.0, "f32")
+        plan.load()
+        plan.run()
+        torch.cuda.synchronize()
+        info = plan.info()
+        assert info["group_width"] == 3 and info["tile_width"] == w, info
+        plan.close()
