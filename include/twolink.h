@@ -167,10 +167,12 @@ int tl_version(void);
 
 /*
  * Environment (read by the library):
- *   TL_TILE="variant,block,tz,grid[,nt[,flip]]"  fix the step tiling of every plan (no tuning);
- *                                    for profiling and sweeps.  Variant 8 (two steps per
- *                                    launch) may name the one-step tiling an odd step count
- *                                    ends with after a ';' (default "0,256,4,0,0,0")
+ *   TL_TILE="variant,block,tz,grid[,nt[,flip[,width]]]"  fix the step tiling of every plan (no
+ *                                    tuning); for profiling and sweeps.  width: RHS per step
+ *                                    group (0 or absent: the plan's groups; 1: every RHS on its
+ *                                    own tiles).  Variant 8 (two steps per launch) may name the
+ *                                    one-step tiling an odd step count ends with after a ';'
+ *                                    (default "0,256,4,0,0,0")
  *   TL_LOG=1                         print autotuning candidates to stderr
  *   TL_FAULT=alloc|launch            make internal allocations or launches fail
  *                                    (read at tl_create; exercises error paths)
