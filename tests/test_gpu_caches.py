@@ -85,7 +85,8 @@ p.load()
 p.run()
 torch.cuda.synchronize()
 info = p.info()
-print(json.dumps({"stats": c.stats(), "tile": [info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip")]}))
+print(json.dumps({"stats": c.stats(), "tile": [info[k] for k in ("variant", "block", "tz", "grid", "nt", "flip",
+                                                                   "tile_width", "group_width")]}))
 """
 
 
@@ -104,5 +105,10 @@ def test_tune_cache_file_skips_the_sweep_in_a_fresh_process(torch, tmp_path):
     assert runs[0]["tile"] == runs[1]["tile"]
     rec = json.loads(cache.read_text())
     assert len(rec) == 1
-    v, b, tz, grid, nt, flip = (int(x) for x in list(rec.values())[0].split(","))
-    assert [v, b, tz, nt, flip] == [runs[0]["tile"][i] for i in (0, 1, 2, 4, 5)]   # the plan reports min(grid, tiles)
+    # "variant,block,tz,grid,nt,flip[,width]", then ";" and the one-step companion of a two-step tiling
+    main = list(rec.values())[0].split(";")[0]
+    f = [int(x) for x in main.split(",")]
+    assert len(f) in (6, 7)
+    width = f[6] if len(f) == 7 and f[6] > 0 else runs[0]["tile"][7]
+    assert f[:3] + f[4:6] == [runs[0]["tile"][i] for i in (0, 1, 2, 4, 5)]   # the plan reports min(grid, tiles)
+    assert width == runs[0]["tile"][6]
