@@ -1331,10 +1331,11 @@ template <> struct LdsVec<double> {
 // The march along the z chain keeps, per thread, its own column: stage s
 // computes step one at march position m = s - 1 (input planes m - 1, m, m + 1)
 // and step two at position m - 1 (step-one planes m - 2, m - 1, m), so a chunk
-// of nz positions runs nz + 2 stages.  The own slots of two LDS buffers hold
-// the input planes m and m - 1, two more the step-one planes m and m - 1; the
-// z two-links of the three links m - 2 .. m + 1 stay in registers.  One
-// barrier per stage.  With one-link fields (D = 1) the chains are all rows and
+// of nz positions runs nz + 2 stages.  Two LDS buffers hold the input planes
+// m (with its outer rows) and m - 1 (own slots), two more the step-one plane
+// m - 1 and, in the thread's own slots, m - 2 (then m).  The z two-links
+// between positions m - 2 .. m + 1 and step one's x two-links stay in
+// registers for step two; its y two-links are reloaded.  One barrier per stage.  With one-link fields (D = 1) the chains are all rows and
 // all planes.  XL: every group's rows are 64 sites long (a wave is one row, and the
 // backward x two-link comes from the lane D to the left), fixed at compile time so
 // that no register is set aside for loading it.
