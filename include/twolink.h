@@ -149,7 +149,8 @@ typedef struct {
     int32_t grid;              /* workgroups per step launch */
     int32_t nt;                /* 1: nontemporal output stores */
     int32_t flip;              /* 1: odd steps run in reversed tile and march order */
-    int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN */
+    int32_t launches_per_step; /* 1 for batched plans, n_groups for TL_PLAIN (launches of one
+                                  step each; see steps_per_launch) */
     int32_t steps_per_launch;  /* 2 when each launch runs two steps (variant 8; an odd step count
                                   ends with one launch of a one-step tiling), else 1 */
     int32_t tile_width;        /* RHS per step group in the launches: group_width, or 1 when the
