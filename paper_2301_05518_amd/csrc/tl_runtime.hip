@@ -617,7 +617,7 @@ int plan_autotune(tl_plan* p) {
   if (!(p->flags & (TL_PLAIN | TL_ONE_STEP)) && p->n_steps >= 2 && c->big_lds &&
       !(tl::vprec(p->prec) == tl::F64 && p->width > 1))
     for (int block : {512, 448, 384, 320, 256})
-      for (int tz : {4, 8, 16})
+      for (int tz : {4, 8, 16, 32})
         for (int grid : {0, cu})
           for (int nt : {0, 1})
             for (int flip : {0, 1}) cands2.push_back({8, block, tz, grid, nt, flip, 0});
