@@ -114,7 +114,7 @@ def test_two_steps_rows_of_64(ctx, orc, torch, prec, monkeypatch):
     n, sigma = (5, 0.5) if prec.endswith("-onelink") else (7, 2.5)
     monkeypatch.setenv("TL_TILE", DIRECT)
     ref = smear(ctx, torch, lats, n, sigma, prec, variant=0)
-    for tile in ("8,512,4,0", "8,384,3,0,1,1", "8,192,1,8,0,1", "8,448,16,5,1,0"):
+    for tile in ("8,512,4,0", "8,384,3,0,1,1", "8,192,1,8,0,1", "8,448,16,5,1,0", "8,512,2,3,0,1"):
         monkeypatch.setenv("TL_TILE", tile)
         log(f"two steps per launch, rows of 64, {prec}: tile {tile}")
         out = smear(ctx, torch, lats, n, sigma, prec, variant=8)
