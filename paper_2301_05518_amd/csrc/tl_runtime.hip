@@ -584,8 +584,17 @@ int plan_autotune(tl_plan* p) {
   const std::string key = tune_key(p);
   auto hit = c->tune.find(key);
   if (hit != c->tune.end()) {
-    c->stats.tune_hits++;
-    return upload_tuned(p, hit->second);
+    // a cached tiling that does not apply to this plan (a cache file written by another
+    // version of the library, or edited) is dropped and the plan tuned again
+    const char* why = nullptr;
+    const Tuned& tu = hit->second;
+    if (tiling_applies(p, tu.cfg, &why) && (tu.cfg.variant != 8 || tiling_applies(p, tu.single, &why))) {
+      c->stats.tune_hits++;
+      return upload_tuned(p, tu);
+    }
+    if (c->log) fprintf(stderr, "[twolink] tune %s: cached tiling %s does not apply (%s), tuning again\n", key.c_str(),
+                        cfg_text(tu.cfg).c_str(), why);
+    c->tune.erase(hit);
   }
   c->stats.tune_sweeps++;
   std::vector<StepConfig> cands, cands2;

@@ -79,8 +79,8 @@ L = (16, 12, 8, 2)
 U = synth.gauge_field(L, "haar", 8200)
 psi = synth.random_field(np.random.default_rng([8201]), (3, L[2], L[1], L[0], 3))
 c = tl.Context(0)
-W = c.build_twolinks(L, torch.from_numpy(U).cuda(), "bf16")
-p = c.plan([tl.Job(L, W, [0, 0, 1], torch.from_numpy(psi).cuda())], 8, 2.0, "bf16", tl.TL_AUTOTUNE | tl.TL_GRAPH)
+W = c.build_twolinks(L, torch.from_numpy(U).cuda(), PREC)
+p = c.plan([tl.Job(L, W, [0, 0, 1], torch.from_numpy(psi).cuda())], 8, 2.0, PREC, tl.TL_AUTOTUNE | tl.TL_GRAPH)
 p.load()
 p.run()
 torch.cuda.synchronize()
@@ -93,7 +93,7 @@ print(json.dumps({"stats": c.stats(), "tile": [info[k] for k in ("variant", "blo
 def test_tune_cache_file_skips_the_sweep_in_a_fresh_process(torch, tmp_path):
     cache = tmp_path / "tune.json"
     env = dict(os.environ, TL_TUNE_CACHE=str(cache))
-    code = CHILD.replace("ROOT", repr(ROOT))
+    code = CHILD.replace("ROOT", repr(ROOT)).replace("PREC", repr("bf16"))
     runs = []
     for k in range(2):
         res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
@@ -112,3 +112,29 @@ def test_tune_cache_file_skips_the_sweep_in_a_fresh_process(torch, tmp_path):
     width = f[6] if len(f) == 7 and f[6] > 0 else runs[0]["tile"][7]
     assert f[:3] + f[4:6] == [runs[0]["tile"][i] for i in (0, 1, 2, 4, 5)]   # the plan reports min(grid, tiles)
     assert width == runs[0]["tile"][6]
+
+
+def test_tune_cache_entry_that_does_not_apply_is_tuned_again(torch, tmp_path):
+    """A cache file entry naming a valid tiling that this plan cannot run (an FP64 plan with two
+    RHS per group, and an LDS-staged variant, which takes FP64 groups of one RHS) is dropped:
+    the plan is tuned again and the file gets the new winner."""
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, TL_TUNE_CACHE=str(cache))
+    code = CHILD.replace("ROOT", repr(ROOT)).replace("PREC", repr("f64"))
+
+    def child():
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        assert res.returncode == 0, res.stderr[-2000:]
+        return json.loads(res.stdout.strip().splitlines()[-1])
+
+    first = child()
+    rec = json.loads(cache.read_text())
+    assert len(rec) == 1 and first["tile"][7] == 2
+    key = list(rec)[0]
+    cache.write_text(json.dumps({key: "7,512,4,0,0,0"}))
+    second = child()
+    log(f"first {first}, second {second}")
+    assert second["stats"]["tune_sweeps"] == 1 and second["stats"]["tune_hits"] == 0
+    if second["tile"][0] >= 5:   # an LDS-staged winner runs every RHS on its own tiles
+        assert second["tile"][6] == 1
+    assert json.loads(cache.read_text())[key] != "7,512,4,0,0,0"
