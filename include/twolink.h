@@ -181,7 +181,8 @@ int tl_version(void);
  *                                    rewritten after every sweep, so that a later process
  *                                    skips the sweep for batch shapes already tuned (keys name
  *                                    the GPU architecture, precision, group width, launch mode
- *                                    and every group's extents and RHS count)
+ *                                    and every group's extents and RHS count); an entry whose
+ *                                    tiling the plan cannot run is dropped and tuned again
  */
 
 /*
