@@ -1,6 +1,7 @@
 """Seeded random cases through the C ABI: ragged shapes, uneven RHS patterns, every storage
-precision and link form, random tilings of every step variant.  Each tiling must give the
-direct kernel's bits; the direct kernel must match the FP64 oracle within the precision's bound."""
+precision and link form, random tilings of every step variant (one and two steps per launch).
+Each tiling must give the direct kernel's bits; the direct kernel must match the FP64 oracle
+within the precision's bound."""
 import numpy as np
 import pytest
 
@@ -49,6 +50,10 @@ def draw_case(k):
         tz = int(rng.integers(1, 17))
         grid = int(rng.choice([0, 0, 3, 8, 64]))
         tiles.append(f"{v},{block},{tz},{grid},{int(rng.integers(0, 2))},{int(rng.integers(0, 2))}")
+    # and a two-step tiling (variant 8: two steps per launch, a one-step launch for an odd last step)
+    block = int(rng.choice([192, 256, 320, 384, 448, 512]))
+    tz, grid = int(rng.integers(1, 17)), int(rng.choice([0, 0, 3, 8, 64]))
+    tiles.append(f"8,{block},{tz},{grid},{int(rng.integers(0, 2))},{int(rng.integers(0, 2))}")
     return form, L, ts, n, sigma, tiles
 
 
