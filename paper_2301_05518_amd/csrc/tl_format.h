@@ -90,6 +90,35 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
+// One F16S colour vector: the six reals as half quotients q = v / s, s = max |v| (FP32),
+// each q formed as v * (1/s) in FP32 and rounded to FP32, then to half.  A site whose
+// maximum is an FP32 subnormal is first multiplied by 2^64 (exact), so that 1/s cannot
+// overflow.  Returns the word (three half pairs, then the scale's bits) every store of
+// the format writes and every load reads.
+template <typename T>
+__device__ __forceinline__ v4u f16s_encode(const T (&v)[6]) {
+  float f[6];
+  float mx = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 6; c++) {
+    f[c] = (float)v[c];
+    mx = fmaxf(mx, fabsf(f[c]));
+  }
+  const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
+  const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
+  return v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)};
+}
+// Its decoding: each half times the scale, rounded to FP32.
+template <typename T>
+__device__ __forceinline__ void f16s_decode(const v4u p, T (&v)[6]) {
+  const float s = __uint_as_float(p.w);
+  v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
+  v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
+  v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
+}
+
 // Store one word; NT = nontemporal (streamed past the caches: the smearing step's
 // output is not read again until the next step, long after it would be evicted).
 template <bool NT, typename V>
@@ -237,30 +266,12 @@ template <> struct Fmt<F16S> {
   template <typename T>
   __device__ static void load_v(const char* __restrict__ b, int64_t Vp, int64_t i, T (&v)[6]) {
     (void)Vp;
-    const v4u p = ldg<v4u>(b + i * 16);
-    const float s = __uint_as_float(p.w);
-    v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
-    v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
-    v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
+    f16s_decode(ldg<v4u>(b + i * 16), v);
   }
   template <typename T, bool NT = false>
   __device__ static void store_v(char* __restrict__ b, int64_t Vp, int64_t i, const T (&v)[6]) {
     (void)Vp;
-    float f[6];
-    float mx = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) {
-      f[c] = (float)v[c];
-      mx = fmaxf(mx, fabsf(f[c]));
-    }
-    // q = v / s as half, computed as v * (1/s) in FP32.  A site whose maximum is
-    // an FP32 subnormal is first multiplied by 2^64 (exact), so 1/s cannot overflow.
-    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
-    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
-    put<NT>(reinterpret_cast<v4u*>(b) + i,
-            v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
+    put<NT>(reinterpret_cast<v4u*>(b) + i, f16s_encode(v));
   }
 };
 
@@ -506,48 +517,14 @@ template <> struct Planes<F16S> : FullW<Planes<F16S>, 3> {
   }
   template <typename T>
   static __device__ __forceinline__ void load_v(const char* const (&pl)[NV], uint32_t i, T (&v)[6]) {
-    const v4u p = ldg<v4u>(pl[0] + i * 16u);
-    const float s = __uint_as_float(p.w);
-    v[0] = h_to_f32(p.x & 0xffffu) * s; v[1] = h_to_f32(p.x >> 16) * s;
-    v[2] = h_to_f32(p.y & 0xffffu) * s; v[3] = h_to_f32(p.y >> 16) * s;
-    v[4] = h_to_f32(p.z & 0xffffu) * s; v[5] = h_to_f32(p.z >> 16) * s;
+    f16s_decode(ldg<v4u>(pl[0] + i * 16u), v);
   }
   template <typename T, bool NT>
   static __device__ __forceinline__ void store_v(char* const (&pl)[NV], uint32_t i, const T (&v)[6]) {
-    float f[6];
-    float mx = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) {
-      f[c] = (float)v[c];
-      mx = fmaxf(mx, fabsf(f[c]));
-    }
-    // same encoding as Fmt<F16S>::store_v (2^64 pre-scaling of subnormal maxima)
-    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
-    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
-    put<NT>(reinterpret_cast<v4u*>(pl[0] + i * 16u),
-            v4u{pack_h(f[0], f[1]), pack_h(f[2], f[3]), pack_h(f[4], f[5]), __float_as_uint(mx)});
+    put<NT>(reinterpret_cast<v4u*>(pl[0] + i * 16u), f16s_encode(v));
   }
-  static __device__ __forceinline__ void round_v(float (&v)[6]) {
-    float f[6];
-    float mx = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) {
-      f[c] = v[c];
-      mx = fmaxf(mx, fabsf(f[c]));
-    }
-    const float pre = mx < 1.17549435e-38f ? 18446744073709551616.0f : 1.0f;
-    const float inv = mx > 0.0f ? 1.0f / (mx * pre) : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) f[c] = mul_f32(f[c] * pre, inv);
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const uint32_t w = pack_h(f[2 * c], f[2 * c + 1]);
-      v[2 * c] = h_to_f32(w & 0xffffu) * mx;
-      v[2 * c + 1] = h_to_f32(w >> 16) * mx;
-    }
-  }
+  // the value a store and a reload of v give
+  static __device__ __forceinline__ void round_v(float (&v)[6]) { f16s_decode(f16s_encode(v), v); }
 };
 
 template <> struct Planes<BF16> : FullW<Planes<BF16>, 3> {
