@@ -642,18 +642,40 @@ int plan_autotune(tl_plan* p) {
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = fail(c, TL_ERR_HIP, "hipEventCreate failed");
   const int reps = 10;
-  const int g_lim = (p->flags & TL_PLAIN) ? 0 : -1;   // plain mode: time on the first group
-  // time reps launches of p->tile (after two untimed), then compare the output with ref
-  // (have_ref false: keep it as ref instead); ms: per launch
+  // Batched plans time their one launch per step.  Plain plans (one launch per group) time one
+  // group of each distinct lattice shape and weigh it by the number of groups of that shape,
+  // so that the tiling suits every shape of the batch, not only the first.
+  std::vector<std::pair<int, int>> timed{{-1, 1}};   // (group, weight); -1: every group at once
+  if (p->flags & TL_PLAIN) {
+    timed.clear();
+    for (int g = 0; g < (int)p->groups.size(); g++) {
+      const tl_geom& ge = p->jobs[p->groups[g].job].job.g;
+      bool seen = false;
+      for (auto& tw : timed) {
+        const tl_geom& gt = p->jobs[p->groups[tw.first].job].job.g;
+        if (gt.L[0] == ge.L[0] && gt.L[1] == ge.L[1] && gt.L[2] == ge.L[2] && p->groups[tw.first].nr == p->groups[g].nr) {
+          tw.second++;
+          seen = true;
+          break;
+        }
+      }
+      if (!seen) timed.push_back({g, 1});
+    }
+  }
+  // time reps launches of p->tile (after two untimed) for each timed group, then compare the
+  // output with ref (have_ref false: keep it as ref instead); ms: per step
   auto trial = [&](bool have_ref, float* ms, bool* same) -> int {
-    for (int w = 0; w < 2; w++) TL_TRY(plan_step(p, c->stream, p->cur, g_lim, w));
-    (void)hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps; k++) TL_TRY(plan_step(p, c->stream, p->cur, g_lim, k));
-    (void)hipEventRecord(e1, c->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) return fail(c, TL_ERR_HIP, "autotune timing failed");
-    float t = 0.0f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    *ms = t / reps;
+    *ms = 0.0f;
+    for (const auto& tw : timed) {
+      for (int w = 0; w < 2; w++) TL_TRY(plan_step(p, c->stream, p->cur, tw.first, w));
+      (void)hipEventRecord(e0, c->stream);
+      for (int k = 0; k < reps; k++) TL_TRY(plan_step(p, c->stream, p->cur, tw.first, k));
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(c, TL_ERR_HIP, "autotune timing failed");
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *ms += t / reps * tw.second;
+    }
     *same = true;
     if (!have_ref) {
       if (hipMemcpyAsync(ref, p->buf[p->cur ^ 1], p->buf_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
@@ -699,8 +721,8 @@ int plan_autotune(tl_plan* p) {
   if (rc == TL_OK && !cands2.empty()) {
     // reference: two launches of the one-step winner, buffer cur -> cur^1 -> ref
     rc = upload_tiling(p, best_cfg, &p->single);
-    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur], p->buf[p->cur ^ 1], g_lim, 0);
-    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur ^ 1], static_cast<char*>(ref), g_lim, 1);
+    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur], p->buf[p->cur ^ 1], -1, 0);
+    if (rc == TL_OK) rc = plan_launch(p, p->single, c->stream, p->buf[p->cur ^ 1], static_cast<char*>(ref), -1, 1);
     float best2 = 1e30f;
     StepConfig best2_cfg{};
     for (size_t ci = 0; ci < cands2.size() && rc == TL_OK; ci++) {

@@ -162,6 +162,24 @@ def test_smear_modes_bit_identical(ctx, orc, torch):
         assert np.array_equal(outs[name], outs["batched"]), name
 
 
+def test_plain_autotune_uneven_batch(ctx, orc, torch):
+    """Plain launches (one RHS per launch) of an uneven batch, tuned over every lattice shape of
+    the batch: the same bits as batched launches, and the oracle's result."""
+    lats = []
+    for k, (L, ts) in enumerate([((10, 6, 9, 2), [0, 1, 1]), ((8, 8, 6, 1), [0, 0]), ((6, 4, 5, 2), [1])]):
+        U = haar(L, 60 + k)
+        psi = synth.random_field(rng(60 + k), (len(ts), L[2], L[1], L[0], 3))
+        lats.append((L, U, ts, psi))
+    plain = gpu_smear(ctx, lats, 7, 2.5, "f64", MODES["plain+autotune"])
+    batched = gpu_smear(ctx, lats, 7, 2.5, "f64", MODES["batched"])
+    for (L, U, ts, psi), a, b in zip(lats, plain, batched):
+        assert np.array_equal(a, b), L
+        ref = orc.smear_batch(orc.build_twolinks(U), ts, 7, 2.5, psi)
+        mr, l2 = errors(a, ref)
+        log(f"plain+autotune {L}: max-rel {mr:.3e}")
+        assert mr < 1e-12 and l2 < 1e-12
+
+
 def test_side_stream_and_second_context(ctx, orc, torch):
     """A context on a non-default torch stream (and a second context on the same device)
     gives the same bits as the default-stream context; the caller orders the streams."""
