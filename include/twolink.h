@@ -94,8 +94,10 @@ enum { TL_ONELINK = 32 };  /* OR into a precision: a one-link field and the one-
 enum {
     TL_PLAIN = 1u,      /* one right-hand side per launch, RHS in succession, eager launches */
     TL_GRAPH = 2u,      /* capture the n step launches in one HIP graph, replayed per run */
-    TL_AUTOTUNE = 4u,   /* time the candidate tilings once and keep the fastest (cached per context);
-                           for batched plans of two or more steps the candidates include launches
+    TL_AUTOTUNE = 4u,   /* time the candidate tilings once and keep the fastest (cached per context;
+                           with TL_PLAIN timed on one RHS of each lattice shape, weighted by the
+                           shape's RHS count); for batched plans of two or more steps the
+                           candidates include launches
                            that run two steps each (the first step's result kept on chip, rounded
                            to the storage precision exactly as a store would round it, so the
                            result is bit-identical to one step per launch) */
