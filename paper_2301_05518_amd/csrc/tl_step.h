@@ -1285,6 +1285,21 @@ __global__ __launch_bounds__(512) void step_zpipe(const StepGroup* __restrict__ 
 // Colour vectors of one plane of R RHS in LDS, rn = R * slots entries: FP32 as a 16-byte word
 // (colours 0 and 1) and an 8-byte word (colour 2) per entry, each kind in its own array, so a
 // vector is one 128-bit and one 64-bit LDS access; FP64 as three arrays of 16-byte words.
+// With one RHS per group the compiler merges the two directions' z hops of the two-step
+// kernel into one body that picks its link and vector arrays by address, which moves those
+// register arrays to scratch memory.  An empty asm statement that differs between the two
+// branches keeps them apart (one RHS only: with more, the merged form picks values in
+// registers and costs nothing).
+template <int R, int K>
+__device__ __forceinline__ void keep_branch() {
+  if constexpr (R == 1) {
+    if constexpr (K == 0) asm volatile("; z hops of step one, upward march");
+    else if constexpr (K == 1) asm volatile("; z hops of step one, downward march");
+    else if constexpr (K == 2) asm volatile("; z hops of step two, upward march");
+    else asm volatile("; z hops of step two, downward march");
+  }
+}
+
 template <typename real> struct LdsVec;
 template <> struct LdsVec<float> {
   static __device__ __forceinline__ int bytes(int rn) { return 24 * ((rn + 1) & ~1); }   // 16-byte aligned halves
@@ -1535,12 +1550,14 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
             mv_acc(lk[1], ahd[r], acc[r]);
             mdv_acc(lk[0], bh[r], acc[r]);
           }
+          keep_branch<R, 0>();
         } else {
 #pragma unroll
           for (int r = 0; r < R; r++) {
             mv_acc(lk[0], bh[r], acc[r]);
             mdv_acc(lk[1], ahd[r], acc[r]);
           }
+          keep_branch<R, 1>();
         }
       }
       real s1[R][6];
@@ -1624,12 +1641,14 @@ __global__ __launch_bounds__(512) void step_fuse2(const StepGroup* __restrict__ 
               mv_acc(lk[0], s1[r], acc[r]);
               mdv_acc(l0, bh[r], acc[r]);
             }
+            keep_branch<R, 2>();
           } else {
 #pragma unroll
             for (int r = 0; r < R; r++) {
               mv_acc(l0, bh[r], acc[r]);
               mdv_acc(lk[0], s1[r], acc[r]);
             }
+            keep_branch<R, 3>();
           }
           const uint32_t site = (uint32_t)(zb * LxLy + xy);
 #pragma unroll
