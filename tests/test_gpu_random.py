@@ -10,7 +10,7 @@ from tests.gpu_common import errors, gpu_smear, log, to_dev, tol
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 24
+N_CASES = 64
 FORMS = ["f64", "f32", "f16s", "bf16", "f32-w12", "bf16-w12", "f64-onelink", "f32-onelink", "f16s-w12-onelink"]
 
 
@@ -54,6 +54,9 @@ def draw_case(k):
     block = int(rng.choice([192, 256, 320, 384, 448, 512]))
     tz, grid = int(rng.integers(1, 17)), int(rng.choice([0, 0, 3, 8, 64]))
     tiles.append(f"8,{block},{tz},{grid},{int(rng.integers(0, 2))},{int(rng.integers(0, 2))}")
+    if k >= 24 and k % 4 == 0:   # rows of 64 sites: the two-step kernels built for that row length
+        L = (64,) + L[1:]
+        tiles += ["8,512,4,0,1,1", "8,384,3,0,0,1"]
     return form, L, ts, n, sigma, tiles
 
 
