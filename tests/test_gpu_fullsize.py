@@ -126,3 +126,50 @@ def test_workload5_sink_smearing_288rhs(ctx, torch):
     RHS on the first, a middle and the last slice."""
     worst, n = run_workload(ctx, torch, 5, "f32", 6, lambda k: [0, 143, k - 1])
     assert worst < tol("f32", n)
+
+
+def test_64cube_odd_steps_two_step_launches(ctx, torch, monkeypatch):
+    """A 64^3 slice with 3 colour walls and an odd step count (n = 7): three two-step launches
+    and one launch of the named one-step companion give the bits of seven one-step launches
+    and of the autotuned plan; every RHS against the oracle."""
+    import paper_2301_05518_amd as tl
+    L = (64, 64, 64, 1)
+    n, sigma = 7, 0.7
+    u = synth.gauge_slice(L, "haar", 2301055100, 0)
+    psi = np.zeros((3, 64, 64, 64, 3), dtype=np.complex128)
+    for c in range(3):
+        psi[c, ..., c] = 1.0
+    Ud = torch.from_numpy(u[None]).cuda()
+    runs = {"two-step + companion": ("8,384,4,0,1,1;7,512,16,0,1,1", tl.TL_GRAPH),
+            "one-step": ("7,512,16,0,1,1", tl.TL_GRAPH),
+            "autotuned": (None, tl.TL_GRAPH | tl.TL_AUTOTUNE)}
+    outs = {}
+    for name, (tile, flags) in runs.items():
+        if tile is None:
+            monkeypatch.delenv("TL_TILE", raising=False)
+        else:
+            monkeypatch.setenv("TL_TILE", tile)
+        W = ctx.build_twolinks(L, Ud, "f32")
+        job = tl.Job(L, W, [0, 0, 0], torch.from_numpy(psi).cuda())
+        plan = ctx.plan([job], n, sigma, "f32", flags)
+        plan.load()
+        plan.run()
+        plan.store()
+        torch.cuda.synchronize()
+        info = plan.info()
+        log(f"64^3 n=7 {name}: variant {info['variant']}, {info['steps_per_launch']} step(s) per launch")
+        if name == "two-step + companion":
+            assert info["variant"] == 8 and info["steps_per_launch"] == 2
+        outs[name] = job.psi.cpu().numpy()
+        plan.close()
+    for name in runs:
+        assert np.array_equal(outs[name], outs["one-step"]), name
+    orc = core.get()
+    Wo = orc.build_twolinks(u[None])
+    worst = 0.0
+    for c in range(3):
+        ref = orc.smear(Wo, 0, n, sigma, psi[c])
+        mr, l2 = errors(outs["one-step"][c], ref)
+        worst = max(worst, mr, l2)
+    log(f"  max-rel/l2 {worst:.3e}")
+    assert worst < tol("f32", n)
