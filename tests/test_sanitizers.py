@@ -70,3 +70,16 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
     res = subprocess.run([exe], env=env, capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, (res.stdout + res.stderr)[-3000:]
     assert "all passed" in res.stdout
+    # the tuning-cache reader (run by tl_create, also on a host-only context) on valid and
+    # malformed files: truncated, unbalanced quotes, overflowing or surplus fields, an empty
+    # companion tiling, binary bytes, an empty file
+    caches = [b'{"k|1": "8,384,32,256,1,1;7,512,16,256,1,1", "k|2": "4,128,1,256,1,0,1"}',
+              b'{"k": "8,384', b'"', b'{"k": "99999999999999999999,1,2,3"}',
+              b'{"k": "8,384,32,256,1,1;"}', b'{"k": "1,2,3,4,5,6,7,8,9,10"}', b'{"k": "-5,64,1,0"}',
+              bytes(range(256)) * 4, b'']
+    for i, content in enumerate(caches):
+        f = tmp_path / f"tune{i}.json"
+        f.write_bytes(content)
+        res = subprocess.run([exe], env=dict(env, TL_TUNE_CACHE=str(f)), capture_output=True, text=True,
+                             timeout=300)
+        assert res.returncode == 0 and "all passed" in res.stdout, (i, (res.stdout + res.stderr)[-3000:])
