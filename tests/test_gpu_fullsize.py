@@ -173,3 +173,38 @@ def test_64cube_odd_steps_two_step_launches(ctx, torch, monkeypatch):
         worst = max(worst, mr, l2)
     log(f"  max-rel/l2 {worst:.3e}")
     assert worst < tol("f32", n)
+
+
+def test_workload3_two_step_plan_equals_one_step_all_rhs(ctx, torch):
+    """The benchmark's workload (64^3x96, 24 colour walls on 8 slices, n = 60, FP32) as the
+    autotuned plan runs it (two steps per launch) and with one step per launch (TL_ONE_STEP):
+    every site of every RHS bit for bit."""
+    import paper_2301_05518_amd as tl
+    wl = synth.workload(3)
+    lat = wl.lattices[0]
+    dev = torch.device("cuda", 0)
+    slices = sorted(set(lat.t_of_rhs))
+    Lx, Ly, Lz, Lt = lat.L
+    U = torch.zeros((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=torch.complex128, device=dev)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        futs = {t: ex.submit(synth.gauge_slice, lat.L, lat.links, lat.link_seed, t) for t in slices}
+        for t in slices:
+            U[t].copy_(torch.from_numpy(futs[t].result()))
+    src = torch.from_numpy(lat.sources_array()).to(dev)
+    W = ctx.build_twolinks(lat.L, U, "f32", slices=slices)
+    del U
+    outs, infos = [], []
+    for flags in (tl.TL_GRAPH | tl.TL_AUTOTUNE, tl.TL_GRAPH | tl.TL_AUTOTUNE | tl.TL_ONE_STEP):
+        job = tl.Job(lat.L, W, lat.t_of_rhs, src.clone(), slices)
+        plan = ctx.plan([job], wl.n_steps, wl.sigma, "f32", flags)
+        plan.load()
+        plan.run()
+        plan.store()
+        torch.cuda.synchronize()
+        infos.append(plan.info())
+        outs.append(job.psi)
+        plan.close()
+    log(f"workload 3: tuned {infos[0]['variant']} x{infos[0]['steps_per_launch']}, "
+        f"one-step {infos[1]['variant']} x{infos[1]['steps_per_launch']}")
+    assert infos[1]["steps_per_launch"] == 1
+    assert torch.equal(outs[0], outs[1])
