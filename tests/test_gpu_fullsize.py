@@ -103,6 +103,14 @@ def test_workload3_64cube_24rhs(ctx, torch):
     assert worst < tol("f32", n)
 
 
+@pytest.mark.parametrize("prec", ["f16s", "bf16"])
+def test_workload3_16bit_storage(ctx, torch, prec):
+    """Workload 3 stored in F16S and BF16 (tuned, graph): 2 RHS sampled against the oracle."""
+    worst, n = run_workload(ctx, torch, 3, prec, 6, lambda k: [5, k - 1])
+    log(f"workload 3 in {prec}: worst {worst:.3e} (bar {tol(prec, n):.2e})")
+    assert worst < tol(prec, n)
+
+
 def test_workload3_w12(ctx, torch):
     """Workload 3 with twelve-real two-links (FP32 rows, third row rebuilt): 3 RHS sampled."""
     worst, n = run_workload(ctx, torch, 3, "f32-w12", 6, lambda k: [0, 11, k - 1])
